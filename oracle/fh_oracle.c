@@ -1,0 +1,215 @@
+/*
+ * CPU oracle for the frequency-Hough (FH) transform -- TEST INFRASTRUCTURE.
+ *
+ * Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no code, header or table with the GPU
+ * library; the two agree only through the written definition below.
+ *
+ * What it computes (Astone et al., "Method for all-sky searches of continuous
+ * gravitational wave signals using the frequency-Hough transform"):
+ *
+ *   For one sky direction n, every peak (FFT i, natural bin k) of the peakmap
+ *   is Doppler corrected, f' = f / (1 + v_i . n)            (Eq. fdopp)
+ *   and mapped into the (f0, fdot) plane as the stripe
+ *       f' - fdot tau_i - df/2  <=  f0  <  f' - fdot tau_i + df/2
+ *   with tau_i = t_i - t0                                    (Eqs. uno, due)
+ *   Each fine bin (K_f per natural bin, Eq. freqres) of each spin-down row
+ *   whose label lies in the stripe gains w_i (1 when unweighted)
+ *                                                     (Eqs. ncount, ncountadap)
+ *
+ * The stripe edge is evaluated in an exactly specified Q32.32 fixed point so
+ * that integer maps can be compared bit for bit:
+ *   S      = (K_f * T_FFT) * 2^32
+ *   G0_i   = llrint((fdot0 * tau_i) * S),  dG_i = llrint((dfdot * tau_i) * S)
+ *   D      = 1 + ((vx*nx + vy*ny) + vz*nz),  r = 1 / D
+ *   X      = floor(((double)(K_f*k) * r) * 2^32)          (corrected centre)
+ *   L_s    = X - b0*2^32 - K_f*2^31 - G0_i - s*dG_i       (left edge, row s)
+ *   bin b is touched  iff  L_s <= b*2^32 < L_s + K_f*2^32
+ * All double operations are IEEE binary64, round to nearest even, evaluated in
+ * the order written and never contracted into FMAs (build with
+ * -ffp-contract=off).
+ *
+ * The oracle fills every touched fine bin directly (K_f additions per peak and
+ * row), accumulating in double; it is deliberately slow.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO32 4294967296.0
+#define ONE32 ((int64_t)1 << 32)
+
+/* floor(a / 2^32) for any int64 a, written without relying on >> of negatives */
+static int64_t floor_div_2p32(int64_t a)
+{
+    int64_t q = a / ONE32; /* truncates toward zero */
+    if (a % ONE32 != 0 && a < 0) q -= 1;
+    return q;
+}
+
+/* Per-FFT spin-down shifts in Q32.32 fine bins (Eqs. uno and sdstep). */
+void fho_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
+                double fdot0, double dfdot, int64_t *g0, int64_t *dg)
+{
+    double S = ((double)kf * t_fft) * TWO32;
+    for (int32_t i = 0; i < n_fft; ++i) {
+        double tau = t[i] - t0;
+        g0[i] = llrint((fdot0 * tau) * S);
+        dg[i] = llrint((dfdot * tau) * S);
+    }
+}
+
+/* Doppler factor inverse r = 1/(1 + v.n) per FFT (Eq. fdopp). */
+void fho_inv_doppler(int32_t n_fft, const double *v, const double *nhat, double *r)
+{
+    for (int32_t i = 0; i < n_fft; ++i) {
+        const double *vi = v + 3 * (int64_t)i;
+        double d = 1.0 + ((vi[0] * nhat[0] + vi[1] * nhat[1]) + vi[2] * nhat[2]);
+        r[i] = 1.0 / d;
+    }
+}
+
+/* Corrected peak centre in Q32.32 fine bins. */
+int64_t fho_center(int32_t k, int32_t kf, double r)
+{
+    double x = ((double)((int64_t)kf * (int64_t)k) * r) * TWO32;
+    return (int64_t)floor(x);
+}
+
+/*
+ * Hough map of one sky direction, rows [row_lo, row_hi) only (the other rows
+ * of `out` are left untouched).  out is [ns][nf] row-major, double, and is
+ * zeroed on the selected rows first.  w may be NULL (all weights 1).
+ * Returns 0, or -1 on invalid arguments.
+ */
+int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
+                  const double *t, const double *v, double t_fft, const double *nhat,
+                  const double *w, int32_t kf, int64_t b0, int32_t nf, int32_t ns,
+                  double fdot0, double dfdot, double t0, int32_t row_lo, int32_t row_hi,
+                  double *out)
+{
+    if (n_fft < 0 || kf < 1 || nf < 0 || ns < 0 || row_lo < 0 || row_hi > ns || row_lo > row_hi)
+        return -1;
+    int64_t n_peaks = offsets[n_fft];
+    int64_t *g0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_fft + 1));
+    int64_t *dg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_fft + 1));
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n_fft + 1));
+    int64_t *edge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_peaks + 1));
+    if (!g0 || !dg || !r || !edge) {
+        free(g0); free(dg); free(r); free(edge);
+        return -1;
+    }
+    fho_shifts(n_fft, t, t0, t_fft, kf, fdot0, dfdot, g0, dg);
+    fho_inv_doppler(n_fft, v, nhat, r);
+    /* stripe left edge at fdot = 0: E = X - b0*2^32 - K_f*2^31 */
+    for (int32_t i = 0; i < n_fft; ++i)
+        for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p)
+            edge[p] = fho_center(bins[p], kf, r[i]) - b0 * ONE32 - (int64_t)kf * (ONE32 / 2);
+
+    const int64_t width = (int64_t)kf * ONE32;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t s = row_lo; s < row_hi; ++s) {
+        double *row = out + (int64_t)s * nf;
+        memset(row, 0, sizeof(double) * (size_t)nf);
+        for (int32_t i = 0; i < n_fft; ++i) {
+            int64_t shift = g0[i] + (int64_t)s * dg[i];
+            double wi = w ? w[i] : 1.0;
+            for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
+                int64_t L = edge[p] - shift;
+                /* candidate bins around the edge; membership decided by the test */
+                int64_t first = floor_div_2p32(L);
+                for (int64_t b = first; b <= first + kf; ++b) {
+                    if (b < 0 || b >= nf) continue;
+                    int64_t lab = b * ONE32;
+                    if (L <= lab && lab < L + width) row[b] += wi;
+                }
+            }
+        }
+    }
+    free(g0); free(dg); free(r); free(edge);
+    return 0;
+}
+
+/*
+ * Candidates of one map by exhaustive scan (Sec. "Selection of first level
+ * candidates"): the map's fine-bin axis is cut into sub-bands of `width` bins
+ * (the last one may be shorter).  In each sub-band, over all rows:
+ *   first  = cell with the largest value; ties -> smaller bin, then smaller row
+ *   second = same order over cells with |b - b_first| > excl; it is reported
+ *            only when |b_second - b_first| >= sep (sep < 0 disables it)
+ * out_idx: [n_sb][2][3] = (valid, bin, row); out_val: [n_sb][2].
+ * Returns the number of sub-bands.
+ */
+static int better(double v, int32_t b, int32_t s, double bv, int32_t bb, int32_t bs)
+{
+    if (v != bv) return v > bv;
+    if (b != bb) return b < bb;
+    return s < bs;
+}
+
+int32_t fho_candidates(const double *map, int32_t ns, int32_t nf, int32_t width, int32_t excl,
+                       int32_t sep, int32_t *out_idx, double *out_val)
+{
+    if (width < 1) return -1;
+    int32_t n_sb = (nf + width - 1) / width;
+    for (int32_t j = 0; j < n_sb; ++j) {
+        int32_t lo = j * width, hi = lo + width < nf ? lo + width : nf;
+        int found = 0;
+        double bv = 0;
+        int32_t bb = -1, bs = -1;
+        for (int32_t s = 0; s < ns; ++s)
+            for (int32_t b = lo; b < hi; ++b) {
+                double x = map[(int64_t)s * nf + b];
+                if (!found || better(x, b, s, bv, bb, bs)) {
+                    found = 1; bv = x; bb = b; bs = s;
+                }
+            }
+        int32_t *o = out_idx + 6 * (int64_t)j;
+        o[0] = found; o[1] = bb; o[2] = bs;
+        out_val[2 * j] = bv;
+        int found2 = 0;
+        double cv = 0;
+        int32_t cb = -1, cs = -1;
+        if (found && sep >= 0) {
+            for (int32_t s = 0; s < ns; ++s)
+                for (int32_t b = lo; b < hi; ++b) {
+                    int32_t d = b > bb ? b - bb : bb - b;
+                    if (d <= excl) continue;
+                    double x = map[(int64_t)s * nf + b];
+                    if (!found2 || better(x, b, s, cv, cb, cs)) {
+                        found2 = 1; cv = x; cb = b; cs = s;
+                    }
+                }
+            if (found2) {
+                int32_t d = cb > bb ? cb - bb : bb - cb;
+                if (d < sep) found2 = 0;
+            }
+        }
+        o[3] = found2; o[4] = found2 ? cb : -1; o[5] = found2 ? cs : -1;
+        out_val[2 * j + 1] = found2 ? cv : 0.0;
+    }
+    return n_sb;
+}
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* thread control for timing runs */
+void fho_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int32_t fho_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
