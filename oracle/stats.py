@@ -39,15 +39,23 @@ def p_lambda_exact(theta: float, lam: float) -> float:
     return integrate.quad(f, theta, np.inf, limit=200)[0]
 
 
+def p_lambda_paper_integral(theta: float, lam: float) -> float:
+    """The integral the paper expands into Eq. plambda_approx, in which the two
+    neighbouring bins follow the same non-central density as the centre."""
+    cdf = lambda x: integrate.quad(lambda y: _pdf_signal(y, lam), 0.0, x)[0]
+    f = lambda x: _pdf_signal(x, lam) * cdf(x) ** 2
+    return integrate.quad(f, theta, 60.0, limit=200)[0]
+
+
 def hough_mean_std(n_fft: int, eta: float):
     """Eq. houghmean: binomial mean and standard deviation of a map cell."""
     return n_fft * eta, math.sqrt(n_fft * eta * (1.0 - eta))
 
 
-def n_thr(n_fft: int, p_fa: float, theta: float = 2.5, sqrt2: bool = True) -> float:
+def n_thr(n_fft: int, p_fa: float, theta: float = 2.5, sqrt2: bool = True, q=None) -> float:
     """Eq. nthr_gauss (sqrt2=True); sqrt2=False is the reading that reproduces
-    the n_thr column of Table III."""
-    q = p0(theta)
+    the n_thr column of Table III.  q overrides p0(theta)."""
+    q = p0(theta) if q is None else q
     c = math.sqrt(2.0) if sqrt2 else 1.0
     return n_fft * q + c * math.sqrt(n_fft * q * (1 - q)) * special.erfcinv(2 * p_fa)
 
