@@ -1,0 +1,229 @@
+/*
+ * fh.h -- C ABI of the MI355X (gfx950) frequency-Hough library.
+ *
+ * The library computes the frequency-Hough (FH) transform of Astone et al.,
+ * "Method for all-sky searches of continuous gravitational wave signals using
+ * the frequency-Hough transform": for each sky direction it Doppler-corrects
+ * a time-frequency peakmap (Eq. fdopp), maps every peak into the source
+ * (f0, fdot) plane as a stripe one natural bin wide (Eqs. uno, due) at K_f
+ * fine bins per natural bin (Eq. freqres), accumulates the number count or its
+ * weighted form (Eqs. ncount, ncountadap) on a spin-down grid (Eq. sdstep),
+ * and selects candidates per frequency sub-band (Sec. "Selection of first
+ * level candidates").
+ *
+ * Exact integer definition (shared by every entry point):
+ *   tau_i = t_i - t0;  S = (K_f * T_FFT) * 2^32
+ *   G0_i  = llrint((fdot0 * tau_i) * S);   dG_i = llrint((dfdot * tau_i) * S)
+ *   D     = 1 + ((vx*nx + vy*ny) + vz*nz);  r = 1 / D        (IEEE binary64,
+ *   X     = floor(((double)(K_f * k) * r) * 2^32)             no FMA contraction)
+ *   L_s   = X - b0*2^32 - K_f*2^31 - G0_i - s*dG_i
+ *   fine bin b (0 <= b < nf) of row s (0 <= s < ns) gains w_i for peak (i, k)
+ *   iff L_s <= b*2^32 < L_s + K_f*2^32.
+ *   Bin b is labelled f0 = (b0 + b) / (K_f T_FFT); row s is fdot0 + s*dfdot.
+ *
+ * Conventions
+ *   - Every pointer named d_* is device memory on the context's device and is
+ *     owned by the caller; it must stay valid until the work enqueued on the
+ *     given stream has completed.  Pointers without the prefix are host memory,
+ *     read before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Compute calls are
+ *     asynchronous with respect to the host: they validate their host-visible
+ *     arguments, enqueue kernels on `stream` and return.
+ *   - Library workspaces are owned by the context and grow on demand; a call
+ *     that has to grow one first synchronises `stream`.
+ *   - A context may be used by one host thread at a time.
+ *   - Errors: functions return a negative fh_status and set a thread-local
+ *     message read with fh_last_error().  Nothing is enqueued after a failed
+ *     validation.  Conditions that can only be seen on the device (invalid
+ *     weights) set a device-side flag that fh_ctx_check() reports.
+ */
+#ifndef FH_H
+#define FH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FH_OK = 0,
+    FH_E_INVALID = -1,     /* an argument fails validation                     */
+    FH_E_NOMEM = -2,       /* device or host allocation failed                 */
+    FH_E_DEVICE = -3,      /* a HIP runtime call failed                        */
+    FH_E_UNSUPPORTED = -4, /* valid but outside what this build supports       */
+    FH_E_BUSY = -5,        /* serving: request not admissible right now        */
+    FH_E_CANCELLED = -6    /* serving: request was cancelled                   */
+} fh_status;
+
+typedef struct fh_ctx fh_ctx;
+typedef struct fh_peakmap fh_peakmap;
+
+/* Peakmap in CSR form (Sec. "Peakmap", Eq. pm): FFT i owns the natural-bin
+ * indices bins[offsets[i] .. offsets[i+1]).  All arrays are host memory. */
+typedef struct {
+    int32_t n_fft;          /* N >= 1                                               */
+    int64_t n_peaks;        /* P = offsets[N] >= 0                                  */
+    const int64_t *offsets; /* [N+1], offsets[0] = 0, non-decreasing                */
+    const int32_t *bins;    /* [P], k >= 0, strictly ascending within each FFT      */
+    const double *t;        /* [N] FFT time tags t_i in s (finite)                  */
+    const double *v;        /* [N][3] detector velocity / c, equatorial, |v| < 1e-2 */
+    double t_fft;           /* T_FFT in s, > 0                                      */
+} fh_peakmap_desc;
+
+/* Search grid of one Hough map (Sec. "Coarse grid in the parameter space"). */
+typedef struct {
+    int32_t kf;    /* K_f fine bins per natural bin, 1 .. 64                   */
+    int64_t b0;    /* absolute index of fine bin 0, 0 <= b0 < 2^28             */
+    int32_t nf;    /* fine bins, 1 .. 2^22                                     */
+    int32_t ns;    /* spin-down rows, 1 .. 2^15                                */
+    double fdot0;  /* spin-down of row 0 [Hz/s]                                */
+    double dfdot;  /* row step [Hz/s]                                          */
+    double t0;     /* reference time [s]                                       */
+} fh_grid;
+
+/* Candidate selection (Sec. "Selection of first level candidates"): the map
+ * is cut into sub-bands of `width` fine bins (the last may be shorter); per
+ * sub-band the best cell over all rows is rank 0; rank 1 is the best cell
+ * with |b - b_rank0| > excl, kept only if |b - b_rank0| >= sep (sep < 0
+ * disables it).  Ties: larger value, then smaller bin, then smaller row. */
+typedef struct {
+    int32_t width;  /* >= 1                                               */
+    int32_t excl;   /* >= 0, e.g. 4                                       */
+    int32_t sep;    /* e.g. 8; < 0 disables rank 1                        */
+    double theta;   /* peak threshold for the critical ratio, e.g. 2.5    */
+} fh_select;
+
+/* One candidate.  f0 = (b0 + bin)/(K_f T_FFT); fdot = fdot0 + row*dfdot.
+ * value: number count, or weighted count; cr: critical ratio (Eq. cr) --
+ * (n - N p0)/sqrt(N p0 (1-p0)), weighted (n - p0 sum w)/sqrt(p0 (1-p0) sum w^2),
+ * with p0 = e^-t - e^-2t + e^-3t / 3 (Eq. p0).  valid = 0 marks an absent
+ * rank-1 candidate (all other fields are then 0 / -1). */
+typedef struct {
+    int32_t sky, subband, rank, bin, row;
+    float value, cr;
+    int32_t valid;
+} fh_candidate;
+
+/* Scheduling of a multi-sky search. */
+typedef enum {
+    FH_SCHED_PLAIN = 0,      /* one launch sequence per sky direction            */
+    FH_SCHED_PERSISTENT = 1  /* all skies' tiles in one persistent launch        */
+} fh_schedule;
+
+typedef struct {
+    int32_t schedule;    /* fh_schedule                                            */
+    int32_t tile_bins;   /* fine bins per LDS tile; 0 = library choice (autotuned) */
+    int32_t sky_chunk;   /* sky directions per workspace chunk; 0 = library choice */
+    int32_t use_graph;   /* 1: capture the chunk's launches in a hipGraph          */
+} fh_options;
+
+/* Tile / workspace plan reported by fh_plan_query. */
+typedef struct {
+    int32_t tile_rows;       /* spin-down rows per LDS tile                */
+    int32_t tile_bins;       /* fine bins per LDS tile                     */
+    int32_t n_row_blocks;
+    int32_t n_bin_blocks;
+    int64_t workspace_bytes; /* library workspace for one sky direction   */
+    int64_t cell_updates;    /* peaks x rows, per sky direction           */
+} fh_plan_info;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Library version string (static storage). */
+const char *fh_version(void);
+
+/* Message of the last failed call on this thread (static storage, never NULL). */
+const char *fh_last_error(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+fh_status fh_ctx_create(int32_t device, fh_ctx **out);
+
+/* Destroy a context; waits for its device work and frees its workspaces.
+ * Peakmaps uploaded through it must be released first.  NULL is a no-op. */
+void fh_ctx_destroy(fh_ctx *ctx);
+
+/* Synchronise `stream` and report (then clear) the device-side error flag:
+ * FH_E_INVALID if a weight vector used since the last check held a value that
+ * is not finite or outside (0, 65536). */
+fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
+
+/* ---- peakmaps ---------------------------------------------------------- */
+
+/* Validate a host peakmap and copy it to device memory owned by the returned
+ * handle (the copy completes before the call returns; the caller keeps its
+ * arrays).  Rejects unsorted or negative bins, bad offsets, non-finite times
+ * or velocities, |v| >= 1e-2, T_FFT <= 0. */
+fh_status fh_peakmap_upload(fh_ctx *ctx, const fh_peakmap_desc *desc, void *stream,
+                            fh_peakmap **out);
+
+/* Free a peakmap's device memory (after work using it has completed). */
+void fh_peakmap_release(fh_ctx *ctx, fh_peakmap *pm);
+
+/* Device bytes held by a peakmap. */
+int64_t fh_peakmap_bytes(const fh_peakmap *pm);
+
+/* ---- planning ---------------------------------------------------------- */
+
+/* Tile shape and workspace size the library will use for (pm, grid);
+ * tile_bins = 0 lets the library choose. */
+fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *grid,
+                        int32_t tile_bins, fh_plan_info *out);
+
+/* ---- Hough maps (one sky direction) ------------------------------------- */
+
+/* Unweighted number-count map (Eq. ncount): d_map is [ns][nf] int32 row-major
+ * and is fully overwritten.  Bit-exact with the definition above.  nhat is a
+ * host unit vector (| |n| - 1 | < 1e-9). */
+fh_status fh_hough_map_i32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[3],
+                           const fh_grid *grid, int32_t *d_map, void *stream);
+
+/* Weighted map (Eq. ncountadap): d_w is the device float32 weight of each FFT
+ * [N]; d_map is [ns][nf] float32.  Weights are rounded to fixed point with
+ * F = floor(log2((2^32-1) / (m * sum w))) fractional bits (m = 1, or 2 when
+ * a peakmap has adjacent bins), accumulated exactly in 32-bit integers and
+ * converted to float32 once, so each cell is within
+ * (#contributions) * 2^-(F+1) + 2^-24 |value| of the exact sum. */
+fh_status fh_hough_map_f32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[3],
+                           const float *d_w, const fh_grid *grid, float *d_map,
+                           void *stream);
+
+/* ---- candidates (many sky directions) ------------------------------------ */
+
+/* Sub-band candidates of n_sky maps without materialising them.
+ * sky:    host [n_sky][3] unit vectors.
+ * d_w:    NULL (unweighted), or device float32 weights: w_stride = 0 means one
+ *         [N] vector shared by all directions, w_stride = N means [n_sky][N].
+ * d_out:  device [n_sky][n_sb][2] candidates, n_sb = ceil(nf / sel->width).
+ * opts:   NULL for defaults (persistent schedule, library tile choice, graphs).
+ * Unweighted results are bit-exact with the definition above and identical for
+ * both schedules; weighted results are identical for both schedules. */
+fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky,
+                              const double *sky, const float *d_w, int32_t w_stride,
+                              const fh_grid *grid, const fh_select *sel,
+                              const fh_options *opts, fh_candidate *d_out, void *stream);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Device time of the kernels of this context, measured with HIP events
+ * recorded on the stream each kernel is launched on. */
+typedef struct {
+    double tiles_ms;          /* LDS-histogram tile kernels                  */
+    int64_t tiles_launches;
+    double front_ms;          /* shifts, weights, stripe edges, windows      */
+    int64_t front_launches;
+    double select_ms;         /* candidate selection                         */
+    int64_t select_launches;
+    int64_t cell_updates;     /* peaks x rows x directions of timed calls    */
+} fh_profile;
+
+/* enable = 1 starts recording (and clears the totals); 0 stops. */
+fh_status fh_ctx_profile(fh_ctx *ctx, int32_t enable);
+
+/* Synchronise the device and read the totals recorded so far. */
+fh_status fh_ctx_profile_read(fh_ctx *ctx, fh_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FH_H */

@@ -1,0 +1,191 @@
+"""Python front end of the frequency-Hough library.
+
+Thin wrappers over the C ABI (``_lib``): they marshal numpy / torch arguments
+and allocate outputs as torch tensors on the device; every computation runs in
+the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+CANDIDATE_FIELDS = ("sky", "subband", "rank", "bin", "row", "value", "cr", "valid")
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def grid_struct(g) -> _lib.fh_grid:
+    return _lib.fh_grid(int(g.kf), int(g.b0), int(g.nf), int(g.ns), float(g.fdot0),
+                        float(g.dfdot), float(g.t0))
+
+
+def select_struct(sel) -> _lib.fh_select:
+    return _lib.fh_select(int(sel.width), int(sel.excl), int(sel.sep), float(sel.theta))
+
+
+class Context:
+    """An fh_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        h = ctypes.c_void_p()
+        check(_lib.fh_ctx_create(self.device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.fh_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, stream=None):
+        check(_lib.fh_ctx_check(self.handle, _stream(stream)))
+
+    def profile(self, enable: bool):
+        check(_lib.fh_ctx_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        p = _lib.fh_profile()
+        check(_lib.fh_ctx_profile_read(self.handle, ctypes.byref(p)))
+        return {f: getattr(p, f) for f, _ in p._fields_}
+
+    def upload(self, pm, stream=None) -> "DevicePeakmap":
+        return DevicePeakmap(self, pm, stream)
+
+    def plan(self, dpm: "DevicePeakmap", grid, tile_bins: int = 0) -> dict:
+        info = _lib.fh_plan_info()
+        g = grid_struct(grid)
+        check(_lib.fh_plan_query(self.handle, dpm.handle, ctypes.byref(g), int(tile_bins),
+                                 ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+class DevicePeakmap:
+    """A peakmap resident in device memory (fh_peakmap)."""
+
+    def __init__(self, ctx: Context, pm, stream=None):
+        self.ctx = ctx
+        self.n_fft = int(pm.t.shape[0])
+        self.n_peaks = int(pm.bins.shape[0])
+        off = np.ascontiguousarray(pm.offsets, dtype=np.int64)
+        bins = np.ascontiguousarray(pm.bins, dtype=np.int32)
+        t = np.ascontiguousarray(pm.t, dtype=np.float64)
+        v = np.ascontiguousarray(pm.v, dtype=np.float64).reshape(-1, 3)
+        d = _lib.fh_peakmap_desc(self.n_fft, self.n_peaks, off.ctypes.data, bins.ctypes.data,
+                                 t.ctypes.data, v.ctypes.data, float(pm.t_fft))
+        h = ctypes.c_void_p()
+        check(_lib.fh_peakmap_upload(ctx.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def nbytes(self) -> int:
+        return int(_lib.fh_peakmap_bytes(self.handle))
+
+    def release(self):
+        if self.handle:
+            torch.cuda.synchronize()
+            _lib.fh_peakmap_release(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.release()
+        except Exception:
+            pass
+
+
+def _nhat(n) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(n, dtype=np.float64).reshape(3))
+    return (ctypes.c_double * 3)(*a.tolist())
+
+
+def fh_hough_map_i32(ctx: Context, dpm: DevicePeakmap, nhat, grid, out=None, stream=None):
+    """Unweighted Hough map [ns][nf] int32 of one sky direction."""
+    if out is None:
+        out = torch.empty((grid.ns, grid.nf), dtype=torch.int32, device="cuda:%d" % ctx.device)
+    assert out.dtype == torch.int32 and out.is_contiguous() and tuple(out.shape) == (grid.ns, grid.nf)
+    g = grid_struct(grid)
+    check(_lib.fh_hough_map_i32(ctx.handle, dpm.handle, _nhat(nhat), ctypes.byref(g),
+                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def fh_hough_map_f32(ctx: Context, dpm: DevicePeakmap, nhat, weights: torch.Tensor, grid,
+                     out=None, stream=None):
+    """Weighted Hough map [ns][nf] float32; weights: device float32 [N]."""
+    assert weights.dtype == torch.float32 and weights.is_cuda and weights.is_contiguous()
+    assert weights.numel() == dpm.n_fft
+    if out is None:
+        out = torch.empty((grid.ns, grid.nf), dtype=torch.float32, device="cuda:%d" % ctx.device)
+    g = grid_struct(grid)
+    check(_lib.fh_hough_map_f32(ctx.handle, dpm.handle, _nhat(nhat),
+                                ctypes.c_void_p(weights.data_ptr()), ctypes.byref(g),
+                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def n_subbands(grid, sel) -> int:
+    return (int(grid.nf) + int(sel.width) - 1) // int(sel.width)
+
+
+def fh_hough_candidates(ctx: Context, dpm: DevicePeakmap, sky, grid, sel,
+                        weights: Optional[torch.Tensor] = None, schedule: int = 1,
+                        tile_bins: int = 0, sky_chunk: int = 0, use_graph: int = 0,
+                        out=None, stream=None):
+    """Candidates of n_sky maps.  Returns an int32 tensor [n_sky, n_sb, 2, 8]
+    holding fh_candidate records (value and cr are float32 bit patterns;
+    use ``decode_candidates``)."""
+    sky = np.ascontiguousarray(np.asarray(sky, dtype=np.float64).reshape(-1, 3))
+    n_sky = sky.shape[0]
+    n_sb = n_subbands(grid, sel)
+    if out is None:
+        out = torch.empty((n_sky, n_sb, 2, 8), dtype=torch.int32, device="cuda:%d" % ctx.device)
+    w_ptr, w_stride = None, 0
+    if weights is not None:
+        assert weights.dtype == torch.float32 and weights.is_cuda and weights.is_contiguous()
+        if weights.dim() == 2:
+            assert tuple(weights.shape) == (n_sky, dpm.n_fft)
+            w_stride = dpm.n_fft
+        else:
+            assert weights.numel() == dpm.n_fft
+        w_ptr = ctypes.c_void_p(weights.data_ptr())
+    g = grid_struct(grid)
+    s = select_struct(sel)
+    o = _lib.fh_options(int(schedule), int(tile_bins), int(sky_chunk), int(use_graph))
+    check(_lib.fh_hough_candidates(ctx.handle, dpm.handle, n_sky, sky.ctypes.data, w_ptr, w_stride,
+                                   ctypes.byref(g), ctypes.byref(s), ctypes.byref(o),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def decode_candidates(raw: torch.Tensor) -> dict:
+    """Split a [.., 8] int32 candidate tensor into numpy fields."""
+    a = raw.detach().cpu().numpy()
+    out = {}
+    for k, name in enumerate(CANDIDATE_FIELDS):
+        col = a[..., k]
+        out[name] = col.view(np.float32) if name in ("value", "cr") else col
+    return out

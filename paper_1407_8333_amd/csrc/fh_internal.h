@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// frequency-Hough library.  Not part of the public C ABI (include/fh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fh.h"
+
+namespace fh {
+
+// Rows of one LDS tile (lanes 0-15 of each 16-lane group of a wave hold one
+// spin-down row each; the four groups of a wave process four peaks).
+constexpr int kTileRows = 16;
+// Row blocks sharing one peak-window table entry.
+constexpr int kRowBlocksPerGroup = 4;
+// Threads per tile workgroup (16 waves).
+constexpr int kTileThreads = 1024;
+// LDS bytes available to one tile workgroup on gfx950.
+constexpr int kLdsBytes = 163840;
+// Bytes of LDS reserved for the scheduler slot and alignment.
+constexpr int kLdsReserve = 256;
+// Number of XCDs of an MI355X; workgroup w is dispatched to XCD w % 8.
+constexpr int kXcds = 8;
+
+// Per-weight-vector statistics computed on the device.
+struct WeightStats {
+    double sum_w;   // sum of w_i
+    double sum_w2;  // sum of w_i^2
+    int32_t frac_bits;  // F: fixed-point fractional bits of the weights
+    int32_t bad;        // 1 if a weight is not finite or outside (0, 65536)
+};
+
+// Arguments of the tile kernels.
+struct TileArgs {
+    int32_t n_fft;
+    int64_t n_peaks;
+    int32_t kf, nf, ns, W;        // W: fine bins per tile
+    int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
+    int32_t n_slots;              // sky directions in this chunk
+    const int64_t *Y;             // [slot][P] stripe edges (Q32.32, see prep kernel)
+    const int2 *win;              // [slot][nrbg][nbb][N] peak windows
+    const int64_t *dg;            // [N] row step of the stripe edge (Q32.32)
+    const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
+    const WeightStats *ws;        // [slot * ws_stride] or nullptr
+    int32_t ws_stride;            // 0: one shared weight vector, 1: one per slot
+    int32_t *map_i32;             // [ns][nf] (plain map, single slot)
+    float *map_f32;               // [ns][nf]
+    unsigned long long *colmax;   // [slot][nf] packed (value << 32 | ~row)
+    // persistent scheduling
+    const int32_t *order;         // tile ids, grouped per XCD queue
+    const int32_t *queue_start;   // [kXcds + 1]
+    int32_t *queue_ctr;           // [kXcds]
+    int32_t tile_base;            // first tile id of a plain launch
+};
+
+// ---- launchers (fh_kernels.hip) ----
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
+                         double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st);
+hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
+                               int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st);
+hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
+                       const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
+                       const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
+                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st);
+hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
+                          const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+                          int32_t kf, int32_t n_slots, int2 *win, hipStream_t st);
+hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
+                        bool persistent, int32_t n_tiles, int32_t grid_blocks, hipStream_t st);
+hipError_t launch_select(const unsigned long long *colmax, int32_t nf, int32_t n_slots,
+                         const fh_select &sel, int32_t sky_base, int32_t n_fft,
+                         const WeightStats *ws, int32_t ws_stride, fh_candidate *out,
+                         hipStream_t st);
+int tile_lds_bytes(int W, int kf);
+int max_tile_bins(int kf);
+
+}  // namespace fh

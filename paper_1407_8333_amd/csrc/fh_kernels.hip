@@ -1,0 +1,644 @@
+// HIP kernels of the frequency-Hough (FH) library for gfx950 (MI355X).
+//
+// Pipeline for one chunk of sky directions (Sec. "Frequency-Hough transform"):
+//   k_shifts       per FFT: spin-down shifts G0_i, dG_i in Q32.32 fine bins
+//                  (Eqs. uno, sdstep).                        sky independent
+//   k_weight_stats per weight vector: sum w, sum w^2, fixed-point bits F.
+//   k_prep         per (sky, peak): Doppler-corrected stripe edge Y (Eq.
+//                  fdopp, Eq. due) and per (sky, FFT) fixed-point weights.
+//   k_windows      per (sky, row-block group, bin block, FFT): the contiguous
+//                  range of that FFT's peaks whose stripes reach the tile.
+//   k_tiles_*      per tile of 16 rows x W fine bins: LDS histogram of stripe
+//                  starts (one ds_add_u32 per peak and row), then the
+//                  differential +w/-w sum along each row as a width-K_f window
+//                  (Eqs. ncount, ncountadap, freqres); writes the map and/or the
+//                  per-bin maximum over rows.
+//   k_select       per (sky, sub-band): first and second-order candidates
+//                  (Sec. "Selection of first level candidates").
+//
+// All FP64 arithmetic is IEEE round-to-nearest-even with contraction off, so
+// the integer stripe edges agree bit for bit with any other implementation of
+// the same definition.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fh_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace fh {
+
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr int64_t kOne32 = (int64_t)1 << 32;
+
+__device__ __forceinline__ int64_t shr32(int64_t a) { return a >> 32; }  // floor(a / 2^32)
+
+// ----------------------------------------------------------------------------
+// fills (graph-safe replacements for memset)
+
+__global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n, unsigned long long v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ----------------------------------------------------------------------------
+// spin-down shifts: G0_i = rint((fdot0 tau_i) S), dG_i = rint((dfdot tau_i) S),
+// S = (K_f T_FFT) 2^32 (Eqs. uno, sdstep)
+
+__global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, double S,
+                         double fdot0, double dfdot, int64_t *__restrict__ g0,
+                         int64_t *__restrict__ dg) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double tau = t[i] - t0;
+    double a = fdot0 * tau;
+    a = a * S;
+    double b = dfdot * tau;
+    b = b * S;
+    g0[i] = (int64_t)rint(a);
+    dg[i] = (int64_t)rint(b);
+}
+
+// ----------------------------------------------------------------------------
+// weight statistics and fixed-point scale (Eq. ncountadap)
+
+__global__ void k_weight_stats(int32_t n, const float *__restrict__ w, int32_t w_stride,
+                               int32_t mult, WeightStats *__restrict__ ws,
+                               int32_t *__restrict__ err_flag) {
+    const float *wv = w + (int64_t)blockIdx.x * w_stride;
+    double s1 = 0.0, s2 = 0.0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double x = (double)wv[i];
+        if (!(x > 0.0 && x < 65536.0)) bad = 1;  // also catches NaN
+        s1 += x;
+        s2 += x * x;
+    }
+    __shared__ double r1[256], r2[256];
+    __shared__ int rb[256];
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    rb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+            r2[threadIdx.x] += r2[threadIdx.x + o];
+            rb[threadIdx.x] |= rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        WeightStats st;
+        st.sum_w = r1[0];
+        st.sum_w2 = r2[0];
+        st.bad = rb[0];
+        // a cell holds at most mult * sum_i rint(w_i 2^F) <= mult (2^F sum w + N/2)
+        double lim = (4294967295.0 / (double)mult - 0.5 * (double)n) / r1[0];
+        int F = -1;
+        if (!rb[0] && lim >= 1.0) {
+            F = 0;
+            while (F < 40 && ldexp(1.0, F + 1) <= lim) ++F;
+        }
+        if (F < 0) st.bad = 1;
+        st.frac_bits = F < 0 ? 0 : F;
+        ws[blockIdx.x] = st;
+        if (st.bad) atomicOr(err_flag, 1);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// per-peak stripe edge.  For peak (i, k) and sky n:
+//   r = 1 / (1 + ((vx nx + vy ny) + vz nz))                     (Eq. fdopp)
+//   X = floor(((double)(K_f k) r) 2^32)
+//   Y = X - b0 2^32 - K_f 2^31 - G0_i + (2^32 - 1)
+// so that the first fine bin of the stripe in row s is
+//   a_s = ceil((X - b0 2^32 - K_f 2^31 - G0_i - s dG_i) / 2^32)
+//       = floor((Y - s dG_i) / 2^32).
+// One wave per FFT; grid.y = sky slot.
+
+__global__ void __launch_bounds__(256) k_prep(
+    int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ bins, const double *__restrict__ v,
+    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
+    int64_t *__restrict__ Y, const float *__restrict__ w, int32_t w_stride,
+    const WeightStats *__restrict__ ws, int32_t ws_stride, uint32_t *__restrict__ wq) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int slot = blockIdx.y;
+    if (i >= n_fft) return;
+    const double *n = sky + 3 * (int64_t)slot;
+    const double *vi = v + 3 * (int64_t)i;
+    double d = vi[0] * n[0];
+    d = d + vi[1] * n[1];
+    d = d + vi[2] * n[2];
+    d = 1.0 + d;
+    const double r = 1.0 / d;
+    const int64_t c = -b0 * kOne32 - (int64_t)kf * (kOne32 / 2) - g0[i] + (kOne32 - 1);
+    int64_t *Ys = Y + (int64_t)slot * n_peaks;
+    const int64_t e = offsets[i + 1];
+    for (int64_t p = offsets[i] + lane; p < e; p += 64) {
+        double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
+        x = x * kTwo32;
+        Ys[p] = (int64_t)floor(x) + c;
+    }
+    if (w != nullptr && lane == 0) {
+        const WeightStats st = ws[(int64_t)slot * ws_stride];
+        double wi = (double)w[(int64_t)slot * w_stride + i];
+        wq[(int64_t)slot * n_fft + i] = st.bad ? 0u : (uint32_t)rint(ldexp(wi, st.frac_bits));
+    }
+}
+
+// ----------------------------------------------------------------------------
+// peak windows.  A peak reaches tile (row group g, bin block jb) when its
+// stripe start, over the group's rows, meets the tile's LDS columns
+// [0, W + K_f - 1) measured from fine bin jb*W - (K_f - 1).  Stripe starts are
+// monotone in Y, and Y is ascending within an FFT, so the peaks that reach a
+// tile form one contiguous range, found by two binary searches.
+
+__global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
+                          const int64_t *__restrict__ Y, int64_t n_peaks,
+                          const int64_t *__restrict__ dg, int32_t ns, int32_t nrbg, int32_t nbb,
+                          int32_t W, int32_t kf, int2 *__restrict__ win) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nbb * n_fft) return;
+    const int32_t jb = (int32_t)(idx / n_fft);
+    const int32_t i = (int32_t)(idx - (int64_t)jb * n_fft);
+    const int32_t g = blockIdx.y, slot = blockIdx.z;
+    const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
+    int32_t s_hi = s_lo + kRowBlocksPerGroup * kTileRows - 1;
+    if (s_hi > ns - 1) s_hi = ns - 1;
+    const int64_t c0 = (int64_t)jb * W - (kf - 1);
+    const int64_t wc = (int64_t)W + kf - 1;
+    const int64_t q_lo = (int64_t)s_lo * dg[i] + c0 * kOne32;
+    const int64_t q_hi = (int64_t)s_hi * dg[i] + c0 * kOne32;
+    const int64_t *Ys = Y + (int64_t)slot * n_peaks;
+    const int64_t p0 = offsets[i], p1 = offsets[i + 1];
+    // lo: first peak whose larger column is >= 0
+    int64_t a = p0, b = p1;
+    while (a < b) {
+        int64_t m = (a + b) >> 1;
+        int64_t y = Ys[m];
+        int64_t c1 = shr32(y - q_lo), c2 = shr32(y - q_hi);
+        int64_t cmax = c1 > c2 ? c1 : c2;
+        if (cmax >= 0) b = m; else a = m + 1;
+    }
+    const int64_t lo = a;
+    // hi: first peak whose smaller column is >= W + K_f - 1
+    b = p1;
+    while (a < b) {
+        int64_t m = (a + b) >> 1;
+        int64_t y = Ys[m];
+        int64_t c1 = shr32(y - q_lo), c2 = shr32(y - q_hi);
+        int64_t cmin = c1 < c2 ? c1 : c2;
+        if (cmin >= wc) b = m; else a = m + 1;
+    }
+    win[(((int64_t)slot * nrbg + g) * nbb + jb) * n_fft + i] = make_int2((int)lo, (int)a);
+}
+
+// ----------------------------------------------------------------------------
+// tiles
+
+// LDS tile: word (c, j) = c * 16 + j holds the stripe starts of column c
+// (fine bin jb*W - (K_f-1) + c) in row s0 + j; column W + K_f - 1 is a dump
+// column for updates that fall outside the tile.  The 16 lanes of a group
+// address 16 consecutive words, so an LDS atomic of a wave is bank-conflict
+// free whatever the stripe positions are.
+// Wave-uniform loads through the scalar unit: the address must be the same in
+// every lane, and the data must not change while the kernel runs.
+template <class T>
+__device__ __forceinline__ T ld_scalar(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+// Peaks handled per lane group and chunk (4 groups -> 16 peaks per chunk).
+constexpr int kChunkIters = 4;
+
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, int jb,
+                                          uint32_t *__restrict__ lds) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwave = blockDim.x >> 6;
+    const int j = lane & 15;
+    const int grp = lane >> 4;
+    const int W = A.W, kf = A.kf;
+    const int wc = W + kf - 1;
+    const int nwords = kTileRows * (wc + 1);
+
+    for (int x = tid * 4; x < nwords; x += blockDim.x * 4) {
+        if (x + 3 < nwords) {
+            *reinterpret_cast<uint4 *>(lds + x) = make_uint4(0, 0, 0, 0);
+        } else {
+            for (int y = x; y < nwords; ++y) lds[y] = 0;
+        }
+    }
+    __syncthreads();
+
+    const int s0 = rb * kTileRows;
+    const int64_t c0 = (int64_t)jb * W - (kf - 1);
+    const int g = rb / kRowBlocksPerGroup;
+    const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * A.n_fft;
+    const int64_t *__restrict__ Ys = A.Y + (int64_t)slot * A.n_peaks;
+    const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
+    const uint32_t dump = (uint32_t)wc;
+    const uint32_t lane_off = (uint32_t)j;
+
+    // Each wave takes a contiguous run of FFTs, read 64 at a time (one per
+    // lane) into registers.  Its peaks are processed in chunks of 16 (four
+    // per 16-lane group); the stripe edges of the next chunk are loaded while
+    // the current one is accumulated, across FFT boundaries.
+    const int per = (A.n_fft + nwave - 1) / nwave;
+    const int i_begin = wave * per;
+    const int i_end = min(A.n_fft, i_begin + per);
+    const int64_t c0sh = c0 * kOne32;
+    const int64_t row = (int64_t)(s0 + j);
+
+    for (int ib = i_begin; ib < i_end; ib += 64) {
+        const int myi = ib + lane;
+        int2 wl = make_int2(0, 0);
+        int64_t dl = 0;
+        uint32_t vl = 1u;
+        if (myi < i_end) {
+            wl = win[myi];
+            dl = A.dg[myi];
+            if (WEIGHTED) vl = wq[myi];
+        }
+        uint64_t mask = __ballot(wl.x < wl.y);
+        if (mask == 0) continue;
+        int k = __builtin_ctzll(mask);
+        int p0 = __builtin_amdgcn_readlane(wl.x, k);
+        int hi = __builtin_amdgcn_readlane(wl.y, k);
+        auto edge_of = [&](int kk) {
+            const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)dl, kk);
+            const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)(dl >> 32), kk);
+            const int64_t dG = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+            return -(row * dG + c0sh);
+        };
+        int64_t nq = edge_of(k);
+        uint32_t val = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, k) : 1u;
+        int64_t ycur[kChunkIters], ynext[kChunkIters];
+        {
+            const int64_t *base = Ys + p0 + grp;
+#pragma unroll
+            for (int u = 0; u < kChunkIters; ++u) ycur[u] = base[4 * u];
+        }
+        for (;;) {
+            // next chunk position
+            int nk = k, np0 = p0 + 4 * kChunkIters, nhi = hi;
+            bool more = true;
+            if (np0 >= hi) {
+                const uint64_t rest = (k >= 63) ? 0ull : (mask >> (k + 1)) << (k + 1);
+                if (rest == 0) {
+                    more = false;
+                } else {
+                    nk = __builtin_ctzll(rest);
+                    np0 = __builtin_amdgcn_readlane(wl.x, nk);
+                    nhi = __builtin_amdgcn_readlane(wl.y, nk);
+                }
+            }
+            if (more) {
+                const int64_t *base = Ys + np0 + grp;
+#pragma unroll
+                for (int u = 0; u < kChunkIters; ++u) ynext[u] = base[4 * u];
+            }
+            // accumulate the current chunk
+            const int cnt = hi - p0;
+            if (cnt >= 4 * kChunkIters) {
+#pragma unroll
+                for (int u = 0; u < kChunkIters; ++u) {
+                    const uint32_t col = (uint32_t)(int32_t)shr32(ycur[u] + nq);
+                    const uint32_t cu = col < dump ? col : dump;
+                    atomicAdd(lds + cu * kTileRows + lane_off, val);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kChunkIters; ++u) {
+                    if (4 * u + grp < cnt) {
+                        const uint32_t col = (uint32_t)(int32_t)shr32(ycur[u] + nq);
+                        const uint32_t cu = col < dump ? col : dump;
+                        atomicAdd(lds + cu * kTileRows + lane_off, val);
+                    }
+                }
+            }
+            if (!more) break;
+            if (nk != k) {
+                nq = edge_of(nk);
+                if (WEIGHTED) val = (uint32_t)__builtin_amdgcn_readlane(vl, nk);
+            }
+            k = nk;
+            p0 = np0;
+            hi = nhi;
+#pragma unroll
+            for (int u = 0; u < kChunkIters; ++u) ycur[u] = ynext[u];
+        }
+    }
+    __syncthreads();
+
+    // Row sums: H(x) = sum_{c = x}^{x + K_f - 1} P(c), x in [0, W): the +w at
+    // the stripe start and the -w K_f bins later, prefix-summed along the row.
+    const int nseg = blockDim.x / kTileRows;
+    const int seg = tid >> 4;
+    const int len = (W + nseg - 1) / nseg;
+    const int x0 = seg * len;
+    int x1 = x0 + len < W ? x0 + len : W;
+    const int64_t bbase = (int64_t)jb * W;
+    if (bbase + x1 > A.nf) x1 = (int)(A.nf - bbase);
+    const int s = s0 + j;
+    const bool row_ok = s < A.ns;
+    float scale = 1.0f;
+    if (WEIGHTED) scale = ldexpf(1.0f, -A.ws[(int64_t)slot * A.ws_stride].frac_bits);
+    uint32_t acc = 0;
+    if (x0 < x1)
+        for (int c = x0; c < x0 + kf - 1; ++c) acc += lds[c * kTileRows + j];
+    for (int x = x0; x < x1; ++x) {
+        acc += lds[(x + kf - 1) * kTileRows + j];
+        const int64_t b = bbase + x;
+        if (MAP && row_ok) {
+            if (WEIGHTED) A.map_f32[(int64_t)s * A.nf + b] = (float)acc * scale;
+            else A.map_i32[(int64_t)s * A.nf + b] = (int32_t)acc;
+        }
+        if (COLMAX) {
+            unsigned long long key =
+                row_ok ? (((unsigned long long)acc << 32) | (0xFFFFFFFFull - (unsigned)s)) : 0ull;
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                unsigned long long other = __shfl_xor(key, o);
+                key = other > key ? other : key;
+            }
+            if (j == 0) atomicMax(A.colmax + (int64_t)slot * A.nf + b, key);
+        }
+        acc -= lds[x * kTileRows + j];
+    }
+}
+
+__device__ __forceinline__ void decode_tile(const TileArgs &A, int t, int &slot, int &rb, int &jb) {
+    jb = t % A.nbb;
+    const int r = t / A.nbb;
+    rb = r % A.nrb;
+    slot = r / A.nrb;
+}
+
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
+    extern __shared__ uint32_t lds[];
+    int slot, rb, jb;
+    decode_tile(A, A.tile_base + blockIdx.x, slot, rb, jb);
+    tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+}
+
+// Persistent form: one workgroup per CU pops tile ids from the queue of its
+// XCD (workgroups are dispatched round-robin over the 8 XCDs), and steals
+// from the other queues when its own is empty.  Every workgroup leaves the
+// loop once all queues are exhausted.
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_tile;
+    const int home = blockIdx.x % kXcds;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int t = -1;
+            for (int k = 0; k < kXcds && t < 0; ++k) {
+                const int qi = (home + k) % kXcds;
+                const int len = A.queue_start[qi + 1] - A.queue_start[qi];
+                if (__hip_atomic_load(A.queue_ctr + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
+                    continue;
+                const int pos = atomicAdd(A.queue_ctr + qi, 1);
+                if (pos < len) t = A.order[A.queue_start[qi] + pos];
+            }
+            s_tile = t;
+        }
+        __syncthreads();
+        const int t = s_tile;
+        if (t < 0) break;
+        int slot, rb, jb;
+        decode_tile(A, t, slot, rb, jb);
+        tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// candidates per (sky, sub-band)
+
+struct Best {
+    uint32_t val;
+    int32_t bin;
+    int32_t row;
+};
+
+__device__ __forceinline__ bool better(const Best &a, const Best &b) {
+    if (a.val != b.val) return a.val > b.val;
+    if (a.bin != b.bin) return a.bin < b.bin;
+    return a.row < b.row;
+}
+
+__device__ Best block_best(Best m, Best *red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        Best o2;
+        o2.val = __shfl_xor(m.val, o);
+        o2.bin = __shfl_xor(m.bin, o);
+        o2.row = __shfl_xor(m.row, o);
+        if (better(o2, m)) m = o2;
+    }
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = m;
+    __syncthreads();
+    Best r = red[0];
+    for (int k = 1; k < nw; ++k)
+        if (better(red[k], r)) r = red[k];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_select(const unsigned long long *__restrict__ colmax,
+                                                int32_t nf, fh_select sel, int32_t sky_base,
+                                                int32_t n_fft, const WeightStats *__restrict__ ws,
+                                                int32_t ws_stride, fh_candidate *__restrict__ out) {
+    __shared__ Best red[16];
+    const int sb = blockIdx.x, slot = blockIdx.y;
+    const int n_sb = gridDim.x;
+    const int lo = sb * sel.width;
+    const int hi = lo + sel.width < nf ? lo + sel.width : nf;
+    const unsigned long long *cm = colmax + (int64_t)slot * nf;
+    const Best none = {0u, 0x7fffffff, 0x7fffffff};
+    Best m = none;
+    bool any = false;
+    for (int b = lo + threadIdx.x; b < hi; b += blockDim.x) {
+        const unsigned long long k = cm[b];
+        Best c = {(uint32_t)(k >> 32), b, (int32_t)(0xFFFFFFFFu - (uint32_t)k)};
+        if (!any || better(c, m)) { m = c; any = true; }
+    }
+    const Best b1 = block_best(m, red);
+    m = none;
+    any = false;
+    if (sel.sep >= 0) {
+        for (int b = lo + threadIdx.x; b < hi; b += blockDim.x) {
+            const int d = b > b1.bin ? b - b1.bin : b1.bin - b;
+            if (d <= sel.excl) continue;
+            const unsigned long long k = cm[b];
+            Best c = {(uint32_t)(k >> 32), b, (int32_t)(0xFFFFFFFFu - (uint32_t)k)};
+            if (!any || better(c, m)) { m = c; any = true; }
+        }
+    }
+    const Best b2 = block_best(m, red);
+    if (threadIdx.x == 0) {
+        const double th = sel.theta;
+        const double p0 = exp(-th) - exp(-2.0 * th) + exp(-3.0 * th) / 3.0;
+        double scale = 1.0, mu, sd;
+        if (ws != nullptr) {
+            const WeightStats st = ws[(int64_t)slot * ws_stride];
+            scale = ldexp(1.0, -st.frac_bits);
+            mu = p0 * st.sum_w;
+            sd = sqrt(p0 * (1.0 - p0) * st.sum_w2);
+        } else {
+            mu = (double)n_fft * p0;
+            sd = sqrt((double)n_fft * p0 * (1.0 - p0));
+        }
+        fh_candidate *o = out + ((int64_t)(sky_base + slot) * n_sb + sb) * 2;
+        const Best bs[2] = {b1, b2};
+        for (int r = 0; r < 2; ++r) {
+            fh_candidate c;
+            c.sky = sky_base + slot;
+            c.subband = sb;
+            c.rank = r;
+            bool valid = bs[r].bin != 0x7fffffff && hi > lo;
+            if (r == 1) {
+                const int d = bs[1].bin > b1.bin ? bs[1].bin - b1.bin : b1.bin - bs[1].bin;
+                valid = valid && sel.sep >= 0 && d >= sel.sep;
+            }
+            c.valid = valid ? 1 : 0;
+            if (valid) {
+                const double value = ws != nullptr ? (double)(float)((float)bs[r].val * (float)scale)
+                                                   : (double)bs[r].val;
+                c.bin = bs[r].bin;
+                c.row = bs[r].row;
+                c.value = (float)value;
+                c.cr = (float)((value - mu) / sd);
+            } else {
+                c.bin = -1;
+                c.row = -1;
+                c.value = 0.0f;
+                c.cr = 0.0f;
+            }
+            o[r] = c;
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65535 * 16) g = 65535 * 16;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + 1) * 4; }
+
+int max_tile_bins(int kf) {
+    const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dump
+    int w = words - kf;                                           // W + kf - 1 + 1 <= words
+    return (w / 64) * 64;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill_u64<<<grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
+                         double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st) {
+    const double S = ((double)kf * t_fft) * kTwo32;
+    k_shifts<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, t, t0, S, fdot0, dfdot, g0, dg);
+    return hipGetLastError();
+}
+
+hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
+                               int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st) {
+    k_weight_stats<<<n_vec, 256, 0, st>>>(n_fft, w, w_stride, mult, ws, err_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
+                       const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
+                       const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
+                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st) {
+    dim3 grid((n_fft + 3) / 4, n_slots);
+    k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, Y, w, w_stride,
+                                 ws, ws_stride, wq);
+    return hipGetLastError();
+}
+
+hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
+                          const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+                          int32_t kf, int32_t n_slots, int2 *win, hipStream_t st) {
+    dim3 grid(grid_for((int64_t)nbb * n_fft, 256), nrbg, n_slots);
+    k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+    return hipGetLastError();
+}
+
+template <bool Wt, bool M, bool C>
+static hipError_t launch_tiles_t(const TileArgs &a, bool persistent, int32_t n_tiles,
+                                 int32_t grid_blocks, hipStream_t st) {
+    const int lds = tile_lds_bytes(a.W, a.kf);
+    if (persistent) {
+        auto k = k_tiles_persistent<Wt, M, C>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        k<<<grid_blocks, kTileThreads, lds, st>>>(a);
+    } else {
+        auto k = k_tiles_plain<Wt, M, C>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        k<<<n_tiles, kTileThreads, lds, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
+                        bool persistent, int32_t n_tiles, int32_t grid_blocks, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (weighted) {
+        if (want_map && want_colmax) return launch_tiles_t<true, true, true>(a, persistent, n_tiles, grid_blocks, st);
+        if (want_map) return launch_tiles_t<true, true, false>(a, persistent, n_tiles, grid_blocks, st);
+        return launch_tiles_t<true, false, true>(a, persistent, n_tiles, grid_blocks, st);
+    }
+    if (want_map && want_colmax) return launch_tiles_t<false, true, true>(a, persistent, n_tiles, grid_blocks, st);
+    if (want_map) return launch_tiles_t<false, true, false>(a, persistent, n_tiles, grid_blocks, st);
+    return launch_tiles_t<false, false, true>(a, persistent, n_tiles, grid_blocks, st);
+}
+
+hipError_t launch_select(const unsigned long long *colmax, int32_t nf, int32_t n_slots,
+                         const fh_select &sel, int32_t sky_base, int32_t n_fft,
+                         const WeightStats *ws, int32_t ws_stride, fh_candidate *out,
+                         hipStream_t st) {
+    const int n_sb = (nf + sel.width - 1) / sel.width;
+    dim3 grid(n_sb, n_slots);
+    k_select<<<grid, 256, 0, st>>>(colmax, nf, sel, sky_base, n_fft, ws, ws_stride, out);
+    return hipGetLastError();
+}
+
+}  // namespace fh
