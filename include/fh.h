@@ -115,7 +115,9 @@ typedef struct {
     int32_t schedule;    /* fh_schedule                                            */
     int32_t tile_bins;   /* fine bins per LDS tile; 0 = library choice (autotuned) */
     int32_t sky_chunk;   /* sky directions per workspace chunk; 0 = library choice */
-    int32_t use_graph;   /* 1: capture the chunk's launches in a hipGraph          */
+    int32_t use_graph;   /* 1: capture the whole search in a hipGraph on first use
+                            and replay it while every pointer and shape argument
+                            (and the stream) is unchanged                       */
 } fh_options;
 
 /* Tile / workspace plan reported by fh_plan_query. */
@@ -203,6 +205,71 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky,
                               const fh_grid *grid, const fh_select *sel,
                               const fh_options *opts, fh_candidate *d_out, void *stream);
 
+/* ---- serving ------------------------------------------------------------ */
+
+/* A continuous-batching request server over one context.  Requests
+ * (band = a resident peakmap + grid, sky patch, spin-down range) queue on the
+ * host; fh_server_poll admits queued requests in arrival order whenever a lane
+ * (a HIP stream with its own workspace) is free and the HBM footprint of the
+ * work in flight plus the request's fits the budget, launches them, and
+ * returns finished ones.  Admitted requests run concurrently on separate
+ * streams, so requests that arrive while others are on the GPU overlap with
+ * them.  Results are identical to running each request alone with
+ * fh_hough_candidates (same kernels, same integer arithmetic).
+ * All server calls must come from the thread that owns the context. */
+typedef struct fh_server fh_server;
+
+typedef struct {
+    const fh_peakmap *pm;  /* resident peakmap of the request's band            */
+    fh_grid grid;          /* band (b0, nf), spin-down rows, reference time     */
+    fh_select sel;
+    int32_t n_sky;         /* >= 1                                              */
+    const double *sky;     /* host [n_sky][3]; copied by fh_server_submit       */
+    const float *d_w;      /* device weights or NULL (see fh_hough_candidates)  */
+    int32_t w_stride;      /* 0 or N                                            */
+    fh_candidate *d_out;   /* device [n_sky][n_sb][2], caller-owned; valid once
+                              the request's completion has been returned       */
+    uint64_t tag;          /* caller's tag, echoed in the completion            */
+} fh_request;
+
+typedef struct {
+    uint64_t id;
+    uint64_t tag;
+    int32_t status;        /* FH_OK, FH_E_CANCELLED, or the launch error        */
+    int32_t lane;          /* lane that ran it (-1 if never admitted)           */
+    double queue_ms;       /* submit -> admission                               */
+    double latency_ms;     /* submit -> completion seen by fh_server_poll       */
+    double device_ms;      /* device time of the request's launches             */
+    int64_t footprint;     /* HBM bytes charged against the budget              */
+    int64_t cell_updates;
+} fh_completion;
+
+/* hbm_budget: bytes of workspace that in-flight requests may use together;
+ * lanes: concurrent requests (streams), 1 .. 16; max_queue: pending requests
+ * accepted before fh_server_submit returns FH_E_BUSY. */
+fh_status fh_server_create(fh_ctx *ctx, int64_t hbm_budget, int32_t lanes, int32_t max_queue,
+                           fh_server **out);
+
+/* Validate and queue a request; *id receives its id.  FH_E_BUSY when the
+ * queue is full; FH_E_UNSUPPORTED when the request alone exceeds the budget. */
+fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id);
+
+/* Make progress (retire finished lanes, admit and launch queued requests) and
+ * copy up to max finished requests into out; *n receives how many. */
+fh_status fh_server_poll(fh_server *srv, fh_completion *out, int32_t max, int32_t *n);
+
+/* Cancel a queued request (its completion reports FH_E_CANCELLED); FH_E_BUSY
+ * if it is already running, FH_E_INVALID if the id is unknown or finished. */
+fh_status fh_server_cancel(fh_server *srv, uint64_t id);
+
+/* Requests queued, running, and finished but not yet returned. */
+fh_status fh_server_stats(const fh_server *srv, int32_t *queued, int32_t *running,
+                          int32_t *finished, int64_t *bytes_in_flight);
+
+/* Wait for all queued and running requests to finish, then free the server
+ * (completions not yet polled are dropped).  NULL is a no-op. */
+void fh_server_destroy(fh_server *srv);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Device time of the kernels of this context, measured with HIP events
@@ -215,6 +282,8 @@ typedef struct {
     double select_ms;         /* candidate selection                         */
     int64_t select_launches;
     int64_t cell_updates;     /* peaks x rows x directions of timed calls    */
+    double graph_ms;          /* replays of captured searches (use_graph)    */
+    int64_t graph_launches;
 } fh_profile;
 
 /* enable = 1 starts recording (and clears the totals); 0 stops. */

@@ -65,7 +65,21 @@ class fh_profile(ctypes.Structure):
     _fields_ = [("tiles_ms", ctypes.c_double), ("tiles_launches", ctypes.c_int64),
                 ("front_ms", ctypes.c_double), ("front_launches", ctypes.c_int64),
                 ("select_ms", ctypes.c_double), ("select_launches", ctypes.c_int64),
-                ("cell_updates", ctypes.c_int64)]
+                ("cell_updates", ctypes.c_int64), ("graph_ms", ctypes.c_double),
+                ("graph_launches", ctypes.c_int64)]
+
+
+class fh_request(ctypes.Structure):
+    _fields_ = [("pm", ctypes.c_void_p), ("grid", fh_grid), ("sel", fh_select),
+                ("n_sky", ctypes.c_int32), ("sky", ctypes.c_void_p), ("d_w", ctypes.c_void_p),
+                ("w_stride", ctypes.c_int32), ("d_out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class fh_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("lane", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("footprint", ctypes.c_int64), ("cell_updates", ctypes.c_int64)]
 
 
 P = ctypes.c_void_p
@@ -85,6 +99,14 @@ _PROTOS = {
     "fh_hough_candidates": ([P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.POINTER(fh_grid),
                              ctypes.POINTER(fh_select), ctypes.POINTER(fh_options), P, P],
                             ctypes.c_int),
+    "fh_server_create": ([P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)],
+                         ctypes.c_int),
+    "fh_server_submit": ([P, ctypes.POINTER(fh_request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "fh_server_poll": ([P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "fh_server_cancel": ([P, ctypes.c_uint64], ctypes.c_int),
+    "fh_server_stats": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "fh_server_destroy": ([P], None),
     "fh_ctx_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "fh_ctx_profile_read": ([P, ctypes.POINTER(fh_profile)], ctypes.c_int),
 }
@@ -145,3 +167,9 @@ fh_hough_map_f32 = _fwd("fh_hough_map_f32")
 fh_hough_candidates = _fwd("fh_hough_candidates")
 fh_ctx_profile = _fwd("fh_ctx_profile")
 fh_ctx_profile_read = _fwd("fh_ctx_profile_read")
+fh_server_create = _fwd("fh_server_create")
+fh_server_submit = _fwd("fh_server_submit")
+fh_server_poll = _fwd("fh_server_poll")
+fh_server_cancel = _fwd("fh_server_cancel")
+fh_server_stats = _fwd("fh_server_stats")
+fh_server_destroy = _fwd("fh_server_destroy")

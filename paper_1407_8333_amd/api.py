@@ -189,3 +189,57 @@ def decode_candidates(raw: torch.Tensor) -> dict:
         col = a[..., k]
         out[name] = col.view(np.float32) if name in ("value", "cr") else col
     return out
+
+
+class Server:
+    """fh_server: continuous batching of candidate searches over resident peakmaps."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, lanes: int = 4, max_queue: int = 1 << 16):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        check(_lib.fh_server_create(ctx.handle, int(hbm_budget), int(lanes), int(max_queue),
+                                    ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}  # host and device objects a queued request still references
+
+    def submit(self, dpm: DevicePeakmap, sky, grid, sel, out: torch.Tensor,
+               weights: Optional[torch.Tensor] = None, tag: int = 0) -> int:
+        sky = np.ascontiguousarray(np.asarray(sky, dtype=np.float64).reshape(-1, 3))
+        w_ptr, w_stride = None, 0
+        if weights is not None:
+            w_ptr = weights.data_ptr()
+            w_stride = dpm.n_fft if weights.dim() == 2 else 0
+        r = _lib.fh_request(dpm.handle, grid_struct(grid), select_struct(sel), sky.shape[0],
+                            sky.ctypes.data, w_ptr, w_stride, out.data_ptr(), int(tag))
+        rid = ctypes.c_uint64()
+        check(_lib.fh_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[rid.value] = (dpm, out, weights)
+        return rid.value
+
+    def poll(self, max_n: int = 256) -> list:
+        buf = (_lib.fh_completion * max_n)()
+        n = ctypes.c_int32()
+        check(_lib.fh_server_poll(self.handle, buf, max_n, ctypes.byref(n)))
+        res = []
+        for k in range(n.value):
+            c = buf[k]
+            d = {f: getattr(c, f) for f, _ in c._fields_}
+            self._keep.pop(d["id"], None)
+            res.append(d)
+        return res
+
+    def cancel(self, rid: int) -> int:
+        return _lib.fh_server_cancel(self.handle, ctypes.c_uint64(rid))
+
+    def stats(self) -> dict:
+        q, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        b = ctypes.c_int64()
+        check(_lib.fh_server_stats(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f),
+                                   ctypes.byref(b)))
+        return {"queued": q.value, "running": r.value, "finished": f.value, "bytes_in_flight": b.value}
+
+    def close(self):
+        if self.handle:
+            _lib.fh_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()

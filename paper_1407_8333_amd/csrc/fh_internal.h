@@ -75,6 +75,8 @@ hipError_t launch_select(const unsigned long long *colmax, int32_t nf, int32_t n
                          const WeightStats *ws, int32_t ws_stride, fh_candidate *out,
                          hipStream_t st);
 int tile_lds_bytes(int W, int kf);
+// Raise the dynamic-LDS limit of the tile kernels (once per device).
+hipError_t init_kernel_attributes();
 int max_tile_bins(int kf);
 
 }  // namespace fh

@@ -257,13 +257,13 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
 
     // Each wave takes a contiguous run of FFTs, read 64 at a time (one per
     // lane) into registers.  Its peaks are processed in chunks of 16 (four
-    // per 16-lane group); the stripe edges of the next chunk are loaded while
-    // the current one is accumulated, across FFT boundaries.
+    // per 16-lane group) through two register buffers: the stripe edges of
+    // the next chunk are in flight while the current chunk is accumulated,
+    // across FFT boundaries.
     const int per = (A.n_fft + nwave - 1) / nwave;
     const int i_begin = wave * per;
     const int i_end = min(A.n_fft, i_begin + per);
-    const int64_t c0sh = c0 * kOne32;
-    const int64_t row = (int64_t)(s0 + j);
+    const uint32_t jrow = (uint32_t)j;
 
     for (int ib = i_begin; ib < i_end; ib += 64) {
         const int myi = ib + lane;
@@ -275,73 +275,106 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             dl = A.dg[myi];
             if (WEIGHTED) vl = wq[myi];
         }
-        uint64_t mask = __ballot(wl.x < wl.y);
+        const uint64_t mask = __ballot(wl.x < wl.y);
         if (mask == 0) continue;
-        int k = __builtin_ctzll(mask);
-        int p0 = __builtin_amdgcn_readlane(wl.x, k);
-        int hi = __builtin_amdgcn_readlane(wl.y, k);
+
+        // -(row * dG + c0 * 2^32) for this lane's row, row = s0 + j:
+        // the wave-uniform part s0*dG + c0*2^32 on the scalar unit, plus j*dG.
         auto edge_of = [&](int kk) {
-            const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)dl, kk);
-            const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)(dl >> 32), kk);
-            const int64_t dG = (int64_t)(((uint64_t)hi32 << 32) | lo32);
-            return -(row * dG + c0sh);
+            const uint32_t dlo = __builtin_amdgcn_readlane((uint32_t)dl, kk);
+            const int32_t dhi = (int32_t)__builtin_amdgcn_readlane((uint32_t)((uint64_t)dl >> 32), kk);
+            const int64_t dG = (int64_t)(((uint64_t)(uint32_t)dhi << 32) | dlo);
+            const int64_t ndG = -dG;
+            const uint64_t base = (uint64_t)(-((int64_t)s0 * dG + c0 * kOne32));
+            const uint64_t lo = (uint64_t)jrow * (uint32_t)ndG + base;
+            const int32_t hi = __mul24((int)jrow, (int)(ndG >> 32));
+            return (int64_t)(lo + ((uint64_t)(uint32_t)hi << 32));
         };
-        int64_t nq = edge_of(k);
-        uint32_t val = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, k) : 1u;
-        int64_t ycur[kChunkIters], ynext[kChunkIters];
-        {
-            const int64_t *base = Ys + p0 + grp;
-#pragma unroll
-            for (int u = 0; u < kChunkIters; ++u) ycur[u] = base[4 * u];
-        }
-        for (;;) {
-            // next chunk position
-            int nk = k, np0 = p0 + 4 * kChunkIters, nhi = hi;
-            bool more = true;
-            if (np0 >= hi) {
-                const uint64_t rest = (k >= 63) ? 0ull : (mask >> (k + 1)) << (k + 1);
+        struct Pos {
+            int k, p0, hi;
+            bool valid;
+        };
+        auto advance = [&](const Pos &c) {
+            Pos n = c;
+            n.p0 = c.p0 + 4 * kChunkIters;
+            if (n.p0 >= c.hi) {
+                const uint64_t rest = c.k >= 63 ? 0ull : mask & (~0ull << (c.k + 1));
                 if (rest == 0) {
-                    more = false;
+                    n.valid = false;
                 } else {
-                    nk = __builtin_ctzll(rest);
-                    np0 = __builtin_amdgcn_readlane(wl.x, nk);
-                    nhi = __builtin_amdgcn_readlane(wl.y, nk);
+                    n.k = __builtin_ctzll(rest);
+                    n.p0 = __builtin_amdgcn_readlane(wl.x, n.k);
+                    n.hi = __builtin_amdgcn_readlane(wl.y, n.k);
                 }
             }
-            if (more) {
-                const int64_t *base = Ys + np0 + grp;
+            return n;
+        };
+        auto issue = [&](int64_t (&buf)[kChunkIters], const Pos &c) {
+            const int64_t *bp = Ys + c.p0 + grp;
 #pragma unroll
-                for (int u = 0; u < kChunkIters; ++u) ynext[u] = base[4 * u];
-            }
-            // accumulate the current chunk
-            const int cnt = hi - p0;
+            for (int u = 0; u < kChunkIters; ++u) buf[u] = bp[4 * u];
+        };
+        auto accumulate = [&](const int64_t (&buf)[kChunkIters], const Pos &c, int64_t nq,
+                              uint32_t val) {
+            const int cnt = c.hi - c.p0;
             if (cnt >= 4 * kChunkIters) {
 #pragma unroll
                 for (int u = 0; u < kChunkIters; ++u) {
-                    const uint32_t col = (uint32_t)(int32_t)shr32(ycur[u] + nq);
+                    const uint32_t col = (uint32_t)(int32_t)shr32(buf[u] + nq);
                     const uint32_t cu = col < dump ? col : dump;
                     atomicAdd(lds + cu * kTileRows + lane_off, val);
                 }
             } else {
+                // partial chunk: lanes past the window end add to the dump
+                // column (every loaded register is consumed on every path)
 #pragma unroll
                 for (int u = 0; u < kChunkIters; ++u) {
-                    if (4 * u + grp < cnt) {
-                        const uint32_t col = (uint32_t)(int32_t)shr32(ycur[u] + nq);
-                        const uint32_t cu = col < dump ? col : dump;
-                        atomicAdd(lds + cu * kTileRows + lane_off, val);
-                    }
+                    const uint32_t col = (uint32_t)(int32_t)shr32(buf[u] + nq);
+                    uint32_t cu = col < dump ? col : dump;
+                    cu = 4 * u + grp < cnt ? cu : dump;
+                    atomicAdd(lds + cu * kTileRows + lane_off, val);
                 }
             }
-            if (!more) break;
-            if (nk != k) {
-                nq = edge_of(nk);
-                if (WEIGHTED) val = (uint32_t)__builtin_amdgcn_readlane(vl, nk);
+        };
+
+        Pos pa;
+        pa.k = __builtin_ctzll(mask);
+        pa.p0 = __builtin_amdgcn_readlane(wl.x, pa.k);
+        pa.hi = __builtin_amdgcn_readlane(wl.y, pa.k);
+        pa.valid = true;
+        int64_t ya[kChunkIters], yb[kChunkIters];
+        issue(ya, pa);
+        int64_t nqa = edge_of(pa.k);
+        uint32_t va = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, pa.k) : 1u;
+        for (;;) {
+            const Pos pb = advance(pa);
+            int64_t nqb = nqa;
+            uint32_t vb = va;
+            // the next loads are issued on every path (re-reading the current
+            // chunk when there is none) so the wait counts stay exact
+            issue(yb, pb.valid ? pb : pa);
+            if (pb.valid) {
+                if (pb.k != pa.k) {
+                    nqb = edge_of(pb.k);
+                    if (WEIGHTED) vb = (uint32_t)__builtin_amdgcn_readlane(vl, pb.k);
+                }
             }
-            k = nk;
-            p0 = np0;
-            hi = nhi;
-#pragma unroll
-            for (int u = 0; u < kChunkIters; ++u) ycur[u] = ynext[u];
+            accumulate(ya, pa, nqa, va);
+            if (!pb.valid) break;
+            const Pos pn = advance(pb);
+            issue(ya, pn.valid ? pn : pb);
+            if (pn.valid) {
+                if (pn.k != pb.k) {
+                    nqa = edge_of(pn.k);
+                    if (WEIGHTED) va = (uint32_t)__builtin_amdgcn_readlane(vl, pn.k);
+                } else {
+                    nqa = nqb;
+                    va = vb;
+                }
+            }
+            accumulate(yb, pb, nqb, vb);
+            if (!pn.valid) break;
+            pa = pn;
         }
     }
     __syncthreads();
@@ -425,7 +458,8 @@ __global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
         if (t < 0) break;
         int slot, rb, jb;
         decode_tile(A, t, slot, rb, jb);
-        tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        // the tile order may cover more directions than this launch holds
+        if (slot < A.n_slots) tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
         __syncthreads();
     }
 }
@@ -599,23 +633,34 @@ hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *
 }
 
 template <bool Wt, bool M, bool C>
+static hipError_t set_tile_attrs() {
+    const int lds = kLdsBytes - kLdsReserve;
+    hipError_t e = hipFuncSetAttribute((const void *)k_tiles_persistent<Wt, M, C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_tiles_plain<Wt, M, C>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+template <bool Wt, bool M, bool C>
 static hipError_t launch_tiles_t(const TileArgs &a, bool persistent, int32_t n_tiles,
                                  int32_t grid_blocks, hipStream_t st) {
     const int lds = tile_lds_bytes(a.W, a.kf);
-    if (persistent) {
-        auto k = k_tiles_persistent<Wt, M, C>;
-        hipError_t e = hipFuncSetAttribute((const void *)k,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
-        k<<<grid_blocks, kTileThreads, lds, st>>>(a);
-    } else {
-        auto k = k_tiles_plain<Wt, M, C>;
-        hipError_t e = hipFuncSetAttribute((const void *)k,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
-        k<<<n_tiles, kTileThreads, lds, st>>>(a);
-    }
+    if (persistent)
+        k_tiles_persistent<Wt, M, C><<<grid_blocks, kTileThreads, lds, st>>>(a);
+    else
+        k_tiles_plain<Wt, M, C><<<n_tiles, kTileThreads, lds, st>>>(a);
     return hipGetLastError();
+}
+
+hipError_t init_kernel_attributes() {
+    hipError_t e;
+    if ((e = set_tile_attrs<true, true, true>()) != hipSuccess) return e;
+    if ((e = set_tile_attrs<true, true, false>()) != hipSuccess) return e;
+    if ((e = set_tile_attrs<true, false, true>()) != hipSuccess) return e;
+    if ((e = set_tile_attrs<false, true, true>()) != hipSuccess) return e;
+    if ((e = set_tile_attrs<false, true, false>()) != hipSuccess) return e;
+    return set_tile_attrs<false, false, true>();
 }
 
 hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,

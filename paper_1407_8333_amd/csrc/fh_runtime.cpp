@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -112,14 +114,44 @@ struct fh_peakmap {
     int64_t bytes = 0;
 };
 
+// Device and pinned buffers of one in-flight search.  A context owns one;
+// each serving lane owns another.
+struct Workspace {
+    DevBuf g0, dg, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
+    PinnedBuf h_sky, h_order;
+    // tile order of the persistent schedule currently held in `order`
+    int64_t order_slots = -1, order_nrb = -1, order_nbb = -1;
+    size_t device_bytes() const {
+        size_t n = 0;
+        for (const DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+            n += b->bytes;
+        return n;
+    }
+    void release() {
+        for (DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+            b->release();
+        h_sky.release();
+        h_order.release();
+        order_slots = -1;
+    }
+};
+
 struct fh_ctx {
     int32_t device = 0;
     int32_t n_cu = 256;
-    // workspaces
-    DevBuf g0, dg, Y, win, colmax, wq, ws, sky, order, qstart, qctr, err;
-    PinnedBuf h_sky, h_order;
+    Workspace main_ws;
+    Workspace *cur = &main_ws;  // workspace used by the launch sequences
+    DevBuf err;
     // autotuned tile width per problem shape
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
+    // captured searches (fh_options.use_graph), keyed by every argument and
+    // workspace pointer they bake in
+    struct GraphEntry {
+        std::vector<uint64_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
     // event-based timing (fh_ctx_profile)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -181,11 +213,15 @@ fh_status check_sky(const double *n) {
     return FH_OK;
 }
 
-int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested) {
+std::tuple<int, int, int, int, int> tune_key(const fh_peakmap *pm, const fh_grid *g, bool weighted) {
+    return std::make_tuple(pm->n_fft, g->nf, g->ns, g->kf, weighted ? 1 : 0);
+}
+
+int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested,
+                     bool weighted = false) {
     const int wmax = max_tile_bins(g->kf);
     if (requested > 0) return std::min(((requested + 63) / 64) * 64, wmax);
-    auto key = std::make_tuple(pm->n_fft, g->nf, g->ns, g->kf, 0);
-    auto it = ctx->tuned.find(key);
+    auto it = ctx->tuned.find(tune_key(pm, g, weighted));
     if (it != ctx->tuned.end()) return it->second;
     // a tile never needs to be wider than the map
     int w = std::min(wmax, ((g->nf + 63) / 64) * 64);
@@ -193,7 +229,7 @@ int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int re
 }
 
 // kinds of timed spans
-enum { kSpanFront = 0, kSpanTiles = 1, kSpanSelect = 2 };
+enum { kSpanFront = 0, kSpanTiles = 1, kSpanSelect = 2, kSpanGraph = 3 };
 
 hipEvent_t next_event(fh_ctx *ctx) {
     if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -238,33 +274,34 @@ struct ChunkBufs {
 };
 
 fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
-                           int slots, bool weighted, hipStream_t st, ChunkBufs &b) {
+                           int slots, int n_sky, bool weighted, hipStream_t st, ChunkBufs &b) {
     const int64_t N = pm->n_fft;
     fh_status s;
-    if ((s = ctx->g0.ensure(8 * N, st))) return s;
-    if ((s = ctx->dg.ensure(8 * N, st))) return s;
+    if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
+    if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
     // the tile kernels read up to 15 stripe edges past a window's end
-    if ((s = ctx->Y.ensure((size_t)8 * (std::max<int64_t>(1, pm->n_peaks) * slots + 16), st))) return s;
-    if ((s = ctx->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
-    if ((s = ctx->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
-    if ((s = ctx->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
-    if ((s = ctx->ws.ensure(sizeof(WeightStats) * (size_t)slots, st))) return s;
-    if ((s = ctx->sky.ensure((size_t)24 * slots, st))) return s;
-    if ((s = ctx->order.ensure((size_t)4 * p.tiles_per_sky * slots, st))) return s;
-    if ((s = ctx->qstart.ensure(4 * (kXcds + 1), st))) return s;
-    if ((s = ctx->qctr.ensure(4 * kXcds, st))) return s;
+    if ((s = ctx->cur->Y.ensure((size_t)8 * (std::max<int64_t>(1, pm->n_peaks) * slots + 16), st))) return s;
+    if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
+    if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
+    if ((s = ctx->cur->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
+    if ((s = ctx->cur->ws.ensure(sizeof(WeightStats) * (size_t)slots, st))) return s;
+    if ((s = ctx->cur->sky.ensure((size_t)24 * n_sky, st))) return s;
+    if (ctx->cur->order.bytes < (size_t)4 * p.tiles_per_sky * slots) ctx->cur->order_slots = -1;
+    if ((s = ctx->cur->order.ensure((size_t)4 * p.tiles_per_sky * slots, st))) return s;
+    if ((s = ctx->cur->qstart.ensure(4 * (kXcds + 1), st))) return s;
+    if ((s = ctx->cur->qctr.ensure(4 * kXcds, st))) return s;
     if ((s = ctx->err.ensure(4, st))) return s;
-    b.g0 = (int64_t *)ctx->g0.ptr;
-    b.dg = (int64_t *)ctx->dg.ptr;
-    b.Y = (int64_t *)ctx->Y.ptr;
-    b.win = (int2 *)ctx->win.ptr;
-    b.colmax = (unsigned long long *)ctx->colmax.ptr;
-    b.wq = (uint32_t *)ctx->wq.ptr;
-    b.ws = (WeightStats *)ctx->ws.ptr;
-    b.sky = (double *)ctx->sky.ptr;
-    b.order = (int32_t *)ctx->order.ptr;
-    b.qstart = (int32_t *)ctx->qstart.ptr;
-    b.qctr = (int32_t *)ctx->qctr.ptr;
+    b.g0 = (int64_t *)ctx->cur->g0.ptr;
+    b.dg = (int64_t *)ctx->cur->dg.ptr;
+    b.Y = (int64_t *)ctx->cur->Y.ptr;
+    b.win = (int2 *)ctx->cur->win.ptr;
+    b.colmax = (unsigned long long *)ctx->cur->colmax.ptr;
+    b.wq = (uint32_t *)ctx->cur->wq.ptr;
+    b.ws = (WeightStats *)ctx->cur->ws.ptr;
+    b.sky = (double *)ctx->cur->sky.ptr;
+    b.order = (int32_t *)ctx->cur->order.ptr;
+    b.qstart = (int32_t *)ctx->cur->qstart.ptr;
+    b.qctr = (int32_t *)ctx->cur->qctr.ptr;
     b.err = (int32_t *)ctx->err.ptr;
     return FH_OK;
 }
@@ -295,26 +332,62 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     return a;
 }
 
-// Shared front half of every path: shifts, weights, stripe edges, windows.
-fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
-                        int slots, const double *sky_host, const float *d_w, int w_stride,
-                        const ChunkBufs &b, hipStream_t st) {
-    fh_status s = ctx->h_sky.ensure((size_t)24 * slots, st);
+// Copy all sky directions of a call to the device in one go.
+fh_status upload_sky(fh_ctx *ctx, const double *sky_host, int n_sky, const ChunkBufs &b,
+                     hipStream_t st) {
+    fh_status s = ctx->cur->h_sky.ensure((size_t)24 * n_sky, st);
     if (s) return s;
     // the pinned staging buffer may still feed an earlier copy on this stream
     HIP_OK(hipStreamSynchronize(st));
-    std::memcpy(ctx->h_sky.ptr, sky_host, (size_t)24 * slots);
-    HIP_OK(hipMemcpyAsync(b.sky, ctx->h_sky.ptr, (size_t)24 * slots, hipMemcpyHostToDevice, st));
+    std::memcpy(ctx->cur->h_sky.ptr, sky_host, (size_t)24 * n_sky);
+    HIP_OK(hipMemcpyAsync(b.sky, ctx->cur->h_sky.ptr, (size_t)24 * n_sky, hipMemcpyHostToDevice, st));
+    return FH_OK;
+}
+
+// Shared front half of every path: shifts, weights, stripe edges, windows.
+fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
+                        int slots, const double *d_sky, const float *d_w, int w_stride,
+                        const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
     HIP_OK(launch_shifts(pm->n_fft, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.g0, b.dg, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
         HIP_OK(launch_weight_stats(pm->n_fft, n_vec, d_w, w_stride, pm->adjacent ? 2 : 1, b.ws, b.err, st));
-    HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, b.sky, slots,
+    HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
                        g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, st));
+    return FH_OK;
+}
+
+// Tile order of the persistent schedule: tiles sharing (sky, bin block) go to
+// the same XCD queue, so the stripe edges they read stay in that XCD's L2.
+fh_status ensure_order(fh_ctx *ctx, const Plan &p, int slots, const ChunkBufs &b, hipStream_t st) {
+    if (ctx->cur->order_slots == slots && ctx->cur->order_nrb == p.nrb && ctx->cur->order_nbb == p.nbb) return FH_OK;
+    const int64_t n_tiles = p.tiles_per_sky * slots;
+    fh_status s = ctx->cur->h_order.ensure(4 * (size_t)(n_tiles + kXcds + 1), st);
+    if (s) return s;
+    HIP_OK(hipStreamSynchronize(st));
+    int32_t *ho = (int32_t *)ctx->cur->h_order.ptr;
+    std::vector<std::vector<int32_t>> q(kXcds);
+    int64_t grp = 0;
+    for (int sl = 0; sl < slots; ++sl)
+        for (int jb = 0; jb < p.nbb; ++jb, ++grp)
+            for (int rb = 0; rb < p.nrb; ++rb)
+                q[grp % kXcds].push_back((int32_t)(((int64_t)sl * p.nrb + rb) * p.nbb + jb));
+    int32_t *hs = ho + n_tiles;
+    int64_t pos = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        hs[x] = (int32_t)pos;
+        for (int32_t t : q[x]) ho[pos++] = t;
+    }
+    hs[kXcds] = (int32_t)pos;
+    HIP_OK(hipMemcpyAsync(b.order, ho, 4 * (size_t)n_tiles, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(b.qstart, hs, 4 * (kXcds + 1), hipMemcpyHostToDevice, st));
+    ctx->cur->order_slots = slots;
+    ctx->cur->order_nrb = p.nrb;
+    ctx->cur->order_nbb = p.nbb;
     return FH_OK;
 }
 
@@ -329,8 +402,9 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
     const bool weighted = d_w != nullptr;
     const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, 0));
     ChunkBufs b;
-    if ((s = ensure_workspace(ctx, pm, g, p, 1, weighted, st, b))) return s;
-    if ((s = enqueue_front(ctx, pm, g, p, 1, nhat, d_w, 0, b, st))) return s;
+    if ((s = ensure_workspace(ctx, pm, g, p, 1, 1, weighted, st, b))) return s;
+    if ((s = upload_sky(ctx, nhat, 1, b, st))) return s;
+    if ((s = enqueue_front(ctx, pm, g, p, 1, b.sky, d_w, 0, b, st))) return s;
     TileArgs a = tile_args(pm, g, p, 1, b, weighted, 0);
     a.map_i32 = weighted ? nullptr : (int32_t *)out;
     a.map_f32 = weighted ? (float *)out : nullptr;
@@ -340,6 +414,103 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
         HIP_OK(launch_tiles(a, weighted, true, false, false, (int32_t)p.tiles_per_sky, 0, st));
     }
     if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns;
+    return FH_OK;
+}
+
+// chunk: as many directions as a bounded workspace holds (fewer launches,
+// more tiles per persistent launch)
+int default_chunk(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
+    if (requested > 0) return requested;
+    const int64_t per_sky = 8 * pm->n_peaks + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft + 8 * (int64_t)g->nf;
+    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)3 << 30) / std::max<int64_t>(1, per_sky));
+    return (int)std::min<int64_t>(by_mem, 256);
+}
+
+// Enqueue the search of n_sky directions (already uploaded to b.sky) in
+// chunks of `chunk`; sel == nullptr skips candidate selection.
+fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
+                     int n_sky, const float *d_w, int w_stride, int schedule, const fh_select *sel,
+                     fh_candidate *d_out, const ChunkBufs &b, hipStream_t st) {
+    fh_status s;
+    const bool weighted = d_w != nullptr;
+    for (int32_t base = 0; base < n_sky; base += chunk) {
+        const int slots = std::min(chunk, n_sky - base);
+        const float *w = weighted ? d_w + (w_stride ? (int64_t)base * w_stride : 0) : nullptr;
+        if ((s = enqueue_front(ctx, pm, g, p, slots, b.sky + 3 * (int64_t)base, w, w_stride, b, st))) return s;
+        HIP_OK(launch_fill_u64(b.colmax, (int64_t)slots * g->nf, 0ull, st));
+        TileArgs a = tile_args(pm, g, p, slots, b, weighted, w_stride == 0 ? 0 : 1);
+        const int64_t n_tiles = p.tiles_per_sky * slots;
+        if (schedule == FH_SCHED_PERSISTENT) {
+            // one tile order for every chunk; tiles of absent directions are skipped
+            if ((s = ensure_order(ctx, p, chunk, b, st))) return s;
+            HIP_OK(launch_fill_i32(b.qctr, kXcds, 0, st));
+            const int grid_blocks = (int)std::min<int64_t>(ctx->n_cu, p.tiles_per_sky * chunk);
+            Timed timed(ctx, st, kSpanTiles);
+            HIP_OK(launch_tiles(a, weighted, false, true, true, (int32_t)n_tiles, grid_blocks, st));
+        } else {
+            a.tile_base = 0;
+            Timed timed(ctx, st, kSpanTiles);
+            HIP_OK(launch_tiles(a, weighted, false, true, false, (int32_t)n_tiles, 0, st));
+        }
+        if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns * slots;
+        if (sel) {
+            Timed timed_sel(ctx, st, kSpanSelect);
+            HIP_OK(launch_select(b.colmax, g->nf, slots, *sel, base, pm->n_fft, weighted ? b.ws : nullptr,
+                                 weighted ? (w_stride == 0 ? 0 : 1) : 0, d_out, st));
+        }
+    }
+    return FH_OK;
+}
+
+// Tile-width autotuner: times the persistent search of a sample of the
+// directions for each candidate width (multiples of 64 up to what the LDS
+// holds) and keeps the fastest per problem shape and weighting.
+fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sky,
+                   const double *sky, const float *d_w, int w_stride, hipStream_t st) {
+    const bool weighted = d_w != nullptr;
+    const int wmax = max_tile_bins(g->kf);
+    const int wcap = std::min(wmax, std::max(64, ((g->nf + 63) / 64) * 64));
+    std::vector<int> cands;
+    for (int w : {512, 832, 1280, 1792, 2176})
+        if (w < wcap) cands.push_back(w);
+    cands.push_back(wcap);
+    const int sample = std::min(n_sky, 16);
+    const bool was = ctx->profiling;
+    ctx->profiling = false;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best_w = wcap;
+    float best_ms = 0.f;
+    fh_status s = FH_OK;
+    for (int w : cands) {
+        const Plan p = make_plan(*g, w);
+        ChunkBufs b;
+        if ((s = ensure_workspace(ctx, pm, g, p, sample, n_sky, weighted, st, b))) break;
+        if ((s = upload_sky(ctx, sky, sample, b, st))) break;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && s == FH_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) { s = fail(FH_E_DEVICE, "hipEventRecord"); break; }
+            s = run_search(ctx, pm, g, p, sample, sample, d_w, w_stride, FH_SCHED_PERSISTENT, nullptr,
+                           nullptr, b, st);
+            if (s) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                s = fail(FH_E_DEVICE, "autotune timing failed");
+                break;
+            }
+        }
+        if (s) break;
+        if (best_ms == 0.f || ms < best_ms) {
+            best_ms = ms;
+            best_w = w;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->profiling = was;
+    if (s) return s;
+    ctx->tuned[tune_key(pm, g, weighted)] = best_w;
     return FH_OK;
 }
 
@@ -363,6 +534,7 @@ fh_status fh_ctx_create(int32_t device, fh_ctx **out) {
     HIP_OK(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(FH_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    HIP_OK(init_kernel_attributes());
     fh_ctx *c = new fh_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
@@ -384,11 +556,13 @@ void fh_ctx_destroy(fh_ctx *ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->g0, &ctx->dg, &ctx->Y, &ctx->win, &ctx->colmax, &ctx->wq, &ctx->ws,
-                      &ctx->sky, &ctx->order, &ctx->qstart, &ctx->qctr, &ctx->err})
-        b->release();
-    ctx->h_sky.release();
-    ctx->h_order.release();
+    for (auto &e : ctx->graphs) {
+        hipGraphExecDestroy(e.exec);
+        hipGraphDestroy(e.graph);
+    }
+    ctx->graphs.clear();
+    ctx->main_ws.release();
+    ctx->err.release();
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
 }
@@ -544,63 +718,67 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
     if (o.tile_bins < 0 || o.sky_chunk < 0) return fail(FH_E_INVALID, "negative option");
     hipStream_t st = (hipStream_t)stream;
     const bool weighted = d_w != nullptr;
-    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins));
-    // chunk: enough tiles to keep every CU busy, bounded workspace
-    int chunk = o.sky_chunk;
-    if (chunk == 0) {
-        const int64_t per_sky = 8 * pm->n_peaks + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft + 8 * (int64_t)g->nf;
-        const int64_t by_mem = std::max<int64_t>(1, ((int64_t)3 << 30) / std::max<int64_t>(1, per_sky));
-        const int64_t by_tiles = std::max<int64_t>(1, (int64_t)16 * ctx->n_cu / std::max<int64_t>(1, p.tiles_per_sky));
-        chunk = (int)std::min<int64_t>({by_mem, std::max<int64_t>(by_tiles, 4), 256});
-    }
-    if (o.schedule == FH_SCHED_PLAIN) chunk = 1;
+    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g, weighted)) == ctx->tuned.end())
+        if ((s = autotune(ctx, pm, g, n_sky, sky, d_w, w_stride, st))) return s;
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins, weighted));
+    int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(pm, g, p, o.sky_chunk);
     chunk = std::min(chunk, n_sky);
     ChunkBufs b;
-    if ((s = ensure_workspace(ctx, pm, g, p, chunk, weighted, st, b))) return s;
-    for (int32_t base = 0; base < n_sky; base += chunk) {
-        const int slots = std::min(chunk, n_sky - base);
-        const float *w = weighted ? d_w + (w_stride ? (int64_t)base * w_stride : 0) : nullptr;
-        if ((s = enqueue_front(ctx, pm, g, p, slots, sky + 3 * (int64_t)base, w, w_stride, b, st))) return s;
-        HIP_OK(launch_fill_u64(b.colmax, (int64_t)slots * g->nf, 0ull, st));
-        TileArgs a = tile_args(pm, g, p, slots, b, weighted, w_stride == 0 ? 0 : 1);
-        const int64_t n_tiles = p.tiles_per_sky * slots;
-        if (o.schedule == FH_SCHED_PERSISTENT) {
-            // order: tiles sharing (sky, bin block) go to the same XCD queue
-            if ((s = ctx->h_order.ensure(4 * (size_t)(n_tiles + kXcds + 1), st))) return s;
-            int32_t *ho = (int32_t *)ctx->h_order.ptr;
-            std::vector<std::vector<int32_t>> q(kXcds);
-            int64_t grp = 0;
-            for (int sl = 0; sl < slots; ++sl)
-                for (int jb = 0; jb < p.nbb; ++jb, ++grp)
-                    for (int rb = 0; rb < p.nrb; ++rb)
-                        q[grp % kXcds].push_back((int32_t)(((int64_t)sl * p.nrb + rb) * p.nbb + jb));
-            int32_t *hs = ho + n_tiles;
-            int64_t pos = 0;
-            for (int x = 0; x < kXcds; ++x) {
-                hs[x] = (int32_t)pos;
-                for (int32_t t : q[x]) ho[pos++] = t;
-            }
-            hs[kXcds] = (int32_t)pos;
-            HIP_OK(hipMemcpyAsync(b.order, ho, 4 * (size_t)n_tiles, hipMemcpyHostToDevice, st));
-            HIP_OK(hipMemcpyAsync(b.qstart, hs, 4 * (kXcds + 1), hipMemcpyHostToDevice, st));
-            HIP_OK(launch_fill_i32(b.qctr, kXcds, 0, st));
-            const int grid_blocks = (int)std::min<int64_t>(ctx->n_cu, n_tiles);
-            {
-                Timed timed(ctx, st, kSpanTiles);
-                HIP_OK(launch_tiles(a, weighted, false, true, true, (int32_t)n_tiles, grid_blocks, st));
-            }
-            // the pinned order buffer is reused by the next chunk
-            HIP_OK(hipStreamSynchronize(st));
-        } else {
-            a.tile_base = 0;
-            Timed timed(ctx, st, kSpanTiles);
-            HIP_OK(launch_tiles(a, weighted, false, true, false, (int32_t)n_tiles, 0, st));
+    if ((s = ensure_workspace(ctx, pm, g, p, chunk, n_sky, weighted, st, b))) return s;
+    if ((s = upload_sky(ctx, sky, n_sky, b, st))) return s;
+    if (!o.use_graph)
+        return run_search(ctx, pm, g, p, chunk, n_sky, d_w, w_stride, o.schedule, sel, d_out, b, st);
+    if (st == nullptr) return fail(FH_E_INVALID, "use_graph needs a created stream, not the default stream");
+
+    // hipGraph: capture the whole search once, replay it while every argument
+    // and workspace pointer it bakes in is unchanged (sky vectors and weights
+    // are read from device memory at replay time, so their contents may change).
+    if (o.schedule == FH_SCHED_PERSISTENT && (s = ensure_order(ctx, p, chunk, b, st))) return s;
+    auto bits = [](double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; };
+    std::vector<uint64_t> key = {
+        (uint64_t)(uintptr_t)pm, (uint64_t)g->kf, (uint64_t)g->b0, (uint64_t)g->nf, (uint64_t)g->ns,
+        bits(g->fdot0), bits(g->dfdot), bits(g->t0), (uint64_t)sel->width, (uint64_t)(uint32_t)sel->excl,
+        (uint64_t)(uint32_t)sel->sep, bits(sel->theta), (uint64_t)o.schedule, (uint64_t)p.W,
+        (uint64_t)chunk, (uint64_t)n_sky, (uint64_t)(uintptr_t)d_w, (uint64_t)(uint32_t)w_stride,
+        (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
+        (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
+        (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky, (uint64_t)(uintptr_t)b.order,
+        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg};
+    fh_ctx::GraphEntry *ge = nullptr;
+    for (auto &e : ctx->graphs)
+        if (e.key == key) ge = &e;
+    if (!ge) {
+        const bool was = ctx->profiling;
+        ctx->profiling = false;  // no event records inside the capture
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        s = run_search(ctx, pm, g, p, chunk, n_sky, d_w, w_stride, o.schedule, sel, d_out, b, st);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        ctx->profiling = was;
+        if (s) {
+            if (graph) hipGraphDestroy(graph);
+            return s;
         }
-        if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns * slots;
-        Timed timed_sel(ctx, st, kSpanSelect);
-        HIP_OK(launch_select(b.colmax, g->nf, slots, *sel, base, pm->n_fft, weighted ? b.ws : nullptr,
-                             weighted ? (w_stride == 0 ? 0 : 1) : 0, d_out, st));
+        if (e != hipSuccess) return fail(FH_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(FH_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        if (ctx->graphs.size() >= 16) {
+            hipGraphExecDestroy(ctx->graphs.front().exec);
+            hipGraphDestroy(ctx->graphs.front().graph);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({key, graph, exec});
+        ge = &ctx->graphs.back();
     }
+    {
+        Timed timed(ctx, st, kSpanGraph);
+        HIP_OK(hipGraphLaunch(ge->exec, st));
+    }
+    if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns * n_sky;
     return FH_OK;
 }
 
@@ -628,11 +806,278 @@ fh_status fh_ctx_profile_read(fh_ctx *ctx, fh_profile *out) {
         HIP_OK(hipEventElapsedTime(&ms, sp.a, sp.b));
         if (sp.kind == kSpanTiles) { p.tiles_ms += ms; p.tiles_launches++; }
         else if (sp.kind == kSpanFront) { p.front_ms += ms; p.front_launches++; }
+        else if (sp.kind == kSpanGraph) { p.graph_ms += ms; p.graph_launches++; }
         else { p.select_ms += ms; p.select_launches++; }
     }
     p.cell_updates = ctx->prof_updates;
     *out = p;
     return FH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// continuous-batching server
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct ServerRequest {
+    uint64_t id = 0;
+    fh_request r{};
+    std::vector<double> sky;
+    Clock::time_point t_submit, t_admit;
+    int64_t footprint = 0;
+    int32_t chunk = 1;
+    int32_t W = 64;
+    int32_t lane = -1;
+    int32_t status = FH_OK;
+    double device_ms = 0.0, latency_ms = 0.0, queue_ms = 0.0;
+};
+
+struct Lane {
+    hipStream_t st = nullptr;
+    Workspace ws;
+    hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    uint64_t req = 0;  // 0 = idle
+};
+
+// Workspace bytes of one search of `chunk` directions with plan p.
+int64_t search_footprint(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk, int n_sky) {
+    const int64_t N = pm->n_fft;
+    const int64_t per_sky = 8 * std::max<int64_t>(1, pm->n_peaks) + 8 * (int64_t)p.nrbg * p.nbb * N +
+                            8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
+    return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
+}
+
+}  // namespace
+
+struct fh_server {
+    fh_ctx *ctx = nullptr;
+    int64_t budget = 0;
+    int32_t max_queue = 0;
+    std::vector<Lane> lanes;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, ServerRequest> reqs;  // queued, running, finished-unreported
+    std::deque<uint64_t> finished;
+    uint64_t next_id = 1;
+    int64_t in_flight = 0;
+};
+
+namespace {
+
+void retire_lanes(fh_server *srv) {
+    for (size_t li = 0; li < srv->lanes.size(); ++li) {
+        Lane &L = srv->lanes[li];
+        if (!L.req) continue;
+        hipError_t q = hipEventQuery(L.ev_done);
+        if (q == hipErrorNotReady) continue;
+        ServerRequest &R = srv->reqs[L.req];
+        const Clock::time_point now = Clock::now();
+        if (q != hipSuccess) {
+            R.status = FH_E_DEVICE;
+        } else {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, L.ev_start, L.ev_done) == hipSuccess) R.device_ms = ms;
+        }
+        R.latency_ms = ms_between(R.t_submit, now);
+        srv->in_flight -= R.footprint;
+        srv->finished.push_back(R.id);
+        L.req = 0;
+    }
+}
+
+void admit(fh_server *srv) {
+    fh_ctx *ctx = srv->ctx;
+    while (!srv->queue.empty()) {
+        const uint64_t id = srv->queue.front();
+        ServerRequest &R = srv->reqs[id];
+        if (srv->in_flight + R.footprint > srv->budget) break;  // arrival order: wait for memory
+        int li = -1;
+        for (size_t k = 0; k < srv->lanes.size(); ++k)
+            if (!srv->lanes[k].req) { li = (int)k; break; }
+        if (li < 0) break;  // wait for a lane
+        srv->queue.pop_front();
+        Lane &L = srv->lanes[li];
+        R.lane = li;
+        R.t_admit = Clock::now();
+        R.queue_ms = ms_between(R.t_submit, R.t_admit);
+        const fh_request &q = R.r;
+        const Plan p = make_plan(q.grid, R.W);
+        const bool weighted = q.d_w != nullptr;
+        ctx->cur = &L.ws;
+        ChunkBufs b;
+        fh_status s = ensure_workspace(ctx, q.pm, &q.grid, p, R.chunk, q.n_sky, weighted, L.st, b);
+        if (!s) s = upload_sky(ctx, R.sky.data(), q.n_sky, b, L.st);
+        if (!s && hipEventRecord(L.ev_start, L.st) != hipSuccess) s = fail(FH_E_DEVICE, "hipEventRecord");
+        if (!s)
+            s = run_search(ctx, q.pm, &q.grid, p, R.chunk, q.n_sky, q.d_w, q.w_stride,
+                           FH_SCHED_PERSISTENT, &q.sel, q.d_out, b, L.st);
+        if (hipEventRecord(L.ev_done, L.st) != hipSuccess && !s) s = fail(FH_E_DEVICE, "hipEventRecord");
+        ctx->cur = &ctx->main_ws;
+        R.status = s;
+        srv->in_flight += R.footprint;
+        L.req = id;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fh_status fh_server_create(fh_ctx *ctx, int64_t hbm_budget, int32_t lanes, int32_t max_queue,
+                           fh_server **out) {
+    fh_status s;
+    if (!out) return fail(FH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((s = check_ctx(ctx))) return s;
+    if (hbm_budget <= 0) return fail(FH_E_INVALID, "hbm_budget must be > 0");
+    if (lanes < 1 || lanes > 16) return fail(FH_E_INVALID, "lanes=%d outside 1..16", lanes);
+    if (max_queue < 1) return fail(FH_E_INVALID, "max_queue must be >= 1");
+    fh_server *srv = new fh_server();
+    srv->ctx = ctx;
+    srv->budget = hbm_budget;
+    srv->max_queue = max_queue;
+    srv->lanes.resize(lanes);
+    for (Lane &L : srv->lanes) {
+        if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreate(&L.ev_start) != hipSuccess || hipEventCreate(&L.ev_done) != hipSuccess) {
+            fh_server_destroy(srv);
+            return fail(FH_E_DEVICE, "creating the server's streams failed");
+        }
+    }
+    *out = srv;
+    return FH_OK;
+}
+
+fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id) {
+    fh_status s;
+    if (!srv) return fail(FH_E_INVALID, "server is NULL");
+    if (!req || !id) return fail(FH_E_INVALID, "request or id is NULL");
+    fh_ctx *ctx = srv->ctx;
+    if ((s = check_ctx(ctx))) return s;
+    if ((s = check_grid(req->pm, &req->grid))) return s;
+    if (req->n_sky < 1 || !req->sky) return fail(FH_E_INVALID, "request needs n_sky >= 1 and sky");
+    for (int32_t k = 0; k < req->n_sky; ++k)
+        if ((s = check_sky(req->sky + 3 * (int64_t)k))) return s;
+    const fh_select &sel = req->sel;
+    if (sel.width < 1 || sel.excl < 0 || !std::isfinite(sel.theta) || !(sel.theta > 0))
+        return fail(FH_E_INVALID, "selection needs width >= 1, excl >= 0, theta > 0");
+    if (!req->d_out) return fail(FH_E_INVALID, "output pointer is NULL");
+    if (req->d_w && req->w_stride != 0 && req->w_stride != req->pm->n_fft)
+        return fail(FH_E_INVALID, "w_stride must be 0 or n_fft");
+    if ((int32_t)srv->queue.size() >= srv->max_queue) return fail(FH_E_BUSY, "request queue is full");
+    ServerRequest R;
+    R.id = srv->next_id++;
+    R.r = *req;
+    R.sky.assign(req->sky, req->sky + 3 * (int64_t)req->n_sky);
+    R.r.sky = nullptr;
+    R.t_submit = Clock::now();
+    R.W = choose_tile_bins(ctx, req->pm, &req->grid, 0, req->d_w != nullptr);
+    const Plan p = make_plan(req->grid, R.W);
+    // the largest chunk whose footprint fits one lane's share of the budget
+    const int64_t share = srv->budget / (int64_t)srv->lanes.size();
+    int chunk = std::min<int>(req->n_sky, 256);
+    while (chunk > 1 && search_footprint(req->pm, &req->grid, p, chunk, req->n_sky) > share) chunk = (chunk + 1) / 2;
+    R.chunk = chunk;
+    R.footprint = search_footprint(req->pm, &req->grid, p, chunk, req->n_sky);
+    if (R.footprint > srv->budget) {
+        srv->next_id--;
+        return fail(FH_E_UNSUPPORTED, "request needs %lld workspace bytes, over the %lld-byte budget",
+                    (long long)R.footprint, (long long)srv->budget);
+    }
+    *id = R.id;
+    srv->reqs[R.id] = std::move(R);
+    srv->queue.push_back(*id);
+    return FH_OK;
+}
+
+fh_status fh_server_poll(fh_server *srv, fh_completion *out, int32_t max, int32_t *n) {
+    fh_status s;
+    if (!srv || !n) return fail(FH_E_INVALID, "server or n is NULL");
+    *n = 0;
+    if (max > 0 && !out) return fail(FH_E_INVALID, "out is NULL");
+    if ((s = check_ctx(srv->ctx))) return s;
+    retire_lanes(srv);
+    admit(srv);
+    int32_t k = 0;
+    while (k < max && !srv->finished.empty()) {
+        const uint64_t id = srv->finished.front();
+        srv->finished.pop_front();
+        const ServerRequest &R = srv->reqs[id];
+        fh_completion c{};
+        c.id = R.id;
+        c.tag = R.r.tag;
+        c.status = R.status;
+        c.lane = R.lane;
+        c.queue_ms = R.queue_ms;
+        c.latency_ms = R.latency_ms;
+        c.device_ms = R.device_ms;
+        c.footprint = R.footprint;
+        c.cell_updates = R.r.pm->n_peaks * (int64_t)R.r.grid.ns * R.r.n_sky;
+        out[k++] = c;
+        srv->reqs.erase(id);
+    }
+    *n = k;
+    return FH_OK;
+}
+
+fh_status fh_server_cancel(fh_server *srv, uint64_t id) {
+    if (!srv) return fail(FH_E_INVALID, "server is NULL");
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) return fail(FH_E_INVALID, "unknown request id %llu", (unsigned long long)id);
+    for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q) {
+        if (*q == id) {
+            srv->queue.erase(q);
+            it->second.status = FH_E_CANCELLED;
+            it->second.latency_ms = ms_between(it->second.t_submit, Clock::now());
+            srv->finished.push_back(id);
+            return FH_OK;
+        }
+    }
+    for (const Lane &L : srv->lanes)
+        if (L.req == id) return fail(FH_E_BUSY, "request %llu is running", (unsigned long long)id);
+    return fail(FH_E_INVALID, "request %llu has finished", (unsigned long long)id);
+}
+
+fh_status fh_server_stats(const fh_server *srv, int32_t *queued, int32_t *running, int32_t *finished,
+                          int64_t *bytes_in_flight) {
+    if (!srv) return fail(FH_E_INVALID, "server is NULL");
+    int32_t r = 0;
+    for (const Lane &L : srv->lanes) r += L.req ? 1 : 0;
+    if (queued) *queued = (int32_t)srv->queue.size();
+    if (running) *running = r;
+    if (finished) *finished = (int32_t)srv->finished.size();
+    if (bytes_in_flight) *bytes_in_flight = srv->in_flight;
+    return FH_OK;
+}
+
+void fh_server_destroy(fh_server *srv) {
+    if (!srv) return;
+    if (srv->ctx) hipSetDevice(srv->ctx->device);
+    // run everything that was accepted, then release
+    for (;;) {
+        retire_lanes(srv);
+        admit(srv);
+        bool busy = !srv->queue.empty();
+        for (const Lane &L : srv->lanes) busy = busy || L.req != 0;
+        if (!busy) break;
+        for (const Lane &L : srv->lanes)
+            if (L.req) hipEventSynchronize(L.ev_done);
+    }
+    for (Lane &L : srv->lanes) {
+        if (L.st) hipStreamSynchronize(L.st);
+        L.ws.release();
+        if (L.ev_start) hipEventDestroy(L.ev_start);
+        if (L.ev_done) hipEventDestroy(L.ev_done);
+        if (L.st) hipStreamDestroy(L.st);
+    }
+    delete srv;
 }
 
 }  // extern "C"

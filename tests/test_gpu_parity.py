@@ -214,3 +214,30 @@ def test_tile_width_does_not_change_results(ctx):
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
     dpm.release()
+
+
+def test_graph_replays_match_eager(ctx):
+    """A captured search replayed several times, with eager work and new sky
+    vectors between replays, matches the eager result every time."""
+    import torch
+    api = _api()
+    w = synth.workload("sky-100hz", n_fft=600, n_sky=6)
+    dpm = ctx.upload(w.pm)
+    st = torch.cuda.Stream()
+    rng = synth.rng_for(9)
+    wt = torch.as_tensor(w.weights, device="cuda")
+    n_sb = api.n_subbands(w.grid, w.sel)
+    out_g = torch.empty((6, n_sb, 2, 8), dtype=torch.int32, device="cuda")
+    for rep in range(4):
+        sky = synth.sky_uniform(6, rng)
+        with torch.cuda.stream(st):
+            api.fh_hough_candidates(ctx, dpm, sky, w.grid, w.sel, weights=wt, use_graph=1,
+                                    out=out_g, stream=st)
+            ref = api.fh_hough_candidates(ctx, dpm, sky, w.grid, w.sel, weights=wt, use_graph=0,
+                                          stream=st)
+        st.synchronize()
+        assert torch.equal(out_g, ref), rep
+        # eager work on the default stream between replays
+        api.fh_hough_map_i32(ctx, dpm, sky[0], w.grid)
+        torch.cuda.synchronize()
+    dpm.release()

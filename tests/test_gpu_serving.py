@@ -1,0 +1,116 @@
+"""Continuous-batching server: each request's candidates are identical alone
+and in the mix; admission respects the HBM budget; queued requests cancel."""
+import numpy as np
+import pytest
+
+from paper_1407_8333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _band(seed, t_fft, f_lo, n_fft):
+    pm = synth.make_noise_peakmap(n_fft, t_fft, int(f_lo * t_fft) - 60, int((f_lo + 0.25) * t_fft) + 60,
+                                  seed=seed)
+    return pm
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_1407_8333_amd import api
+    ctx = api.Context(0)
+    bands = [_band(1, 8192.0, 60.0, 300), _band(2, 4096.0, 300.0, 500), _band(3, 1024.0, 700.0, 900)]
+    dpms = [ctx.upload(pm) for pm in bands]
+    yield ctx, bands, dpms
+    for d in dpms:
+        d.release()
+    ctx.close()
+
+
+def _requests(bands, rng):
+    reqs = []
+    for k in range(14):
+        bi = k % 3
+        pm = bands[bi]
+        f_lo = pm.k_lo / pm.t_fft + 0.01
+        rng_sd = [(-1e-9, 1e-10), (-1e-8, 1e-9)][k % 2]
+        grid = synth.make_grid(pm, f_lo, f_lo + 0.2, *rng_sd)
+        sel = synth.Selection(width=max(64, grid.nf // 8))
+        n_sky = int(rng.integers(1, 24))
+        sky = synth.sky_uniform(n_sky, rng)
+        weighted = k % 4 == 3
+        reqs.append((bi, grid, sel, sky, weighted))
+    return reqs
+
+
+def test_alone_equals_mix(setup):
+    import torch
+    from paper_1407_8333_amd import api
+    ctx, bands, dpms = setup
+    rng = synth.rng_for(3)
+    reqs = _requests(bands, rng)
+    wts = [torch.as_tensor(synth.fft_weights(pm.n_fft, rng), device="cuda") for pm in bands]
+    alone = []
+    for bi, grid, sel, sky, weighted in reqs:
+        alone.append(api.fh_hough_candidates(ctx, dpms[bi], sky, grid, sel,
+                                             weights=wts[bi] if weighted else None))
+    torch.cuda.synchronize()
+    srv = api.Server(ctx, hbm_budget=1 << 30, lanes=3)
+    outs, ids = [], []
+    for k, (bi, grid, sel, sky, weighted) in enumerate(reqs):
+        out = torch.full((len(sky), api.n_subbands(grid, sel), 2, 8), -7, dtype=torch.int32, device="cuda")
+        outs.append(out)
+        ids.append(srv.submit(dpms[bi], sky, grid, sel, out, weights=wts[bi] if weighted else None, tag=k))
+        if k % 3 == 2:  # requests keep arriving while others run
+            srv.poll()
+    done = {}
+    for _ in range(100000):
+        for c in srv.poll():
+            done[c["tag"]] = c
+        if len(done) == len(reqs):
+            break
+    srv.close()
+    torch.cuda.synchronize()
+    assert len(done) == len(reqs)
+    lanes_used = {c["lane"] for c in done.values()}
+    assert len(lanes_used) > 1
+    for k in range(len(reqs)):
+        assert done[k]["status"] == 0
+        assert done[k]["latency_ms"] >= done[k]["queue_ms"] >= 0
+        assert torch.equal(outs[k], alone[k]), k
+
+
+def test_budget_admission_and_cancel(setup):
+    import torch
+    from paper_1407_8333_amd import _lib, api
+    ctx, bands, dpms = setup
+    pm = bands[1]
+    f_lo = pm.k_lo / pm.t_fft + 0.01
+    grid = synth.make_grid(pm, f_lo, f_lo + 0.2, -1e-8, 1e-9)
+    sel = synth.Selection(width=512)
+    sky = synth.sky_uniform(4, synth.rng_for(5))
+    out0 = torch.empty((4, api.n_subbands(grid, sel), 2, 8), dtype=torch.int32, device="cuda")
+    # a budget below one request's footprint is refused at submit
+    tiny = api.Server(ctx, hbm_budget=1 << 16, lanes=2)
+    with pytest.raises(_lib.FHError) as e:
+        tiny.submit(dpms[1], sky, grid, sel, out0)
+    assert e.value.status == _lib.FH_E_UNSUPPORTED
+    tiny.close()
+    # one lane: the second and third requests wait in the queue
+    srv = api.Server(ctx, hbm_budget=1 << 30, lanes=1)
+    outs = [torch.empty_like(out0) for _ in range(3)]
+    ids = [srv.submit(dpms[1], sky, grid, sel, o, tag=k) for k, o in enumerate(outs)]
+    assert srv.cancel(ids[2]) == 0
+    st = srv.stats()
+    assert st["queued"] + st["running"] <= 2
+    done = {}
+    for _ in range(100000):
+        for c in srv.poll():
+            done[c["tag"]] = c
+        if len(done) == 3:
+            break
+    srv.close()
+    assert done[2]["status"] == _lib.FH_E_CANCELLED
+    assert done[0]["status"] == 0 and done[1]["status"] == 0
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
