@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of one direction the CPU oracle computes (0 = auto)")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests of the Poisson serving run (0 disables it)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured serving capacity")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB moved by one plain device copy before the timed steps "
                          "(reference dispatch for hardware byte counters)")
@@ -86,6 +90,81 @@ def cpu_baseline(w, rows_arg):
             "kind": "oracle",
             "sample": "1 sky direction, spin-down rows 0..%d of %d, %d peaks (%.3g cell updates, %.1f s)"
                       % (rows - 1, grid.ns, w.pm.n_peaks, updates, dt)}
+
+
+SERVE_BANDS = [(8192.0, 40.0), (8192.0, 110.0), (4096.0, 180.0), (4096.0, 450.0),
+               (2048.0, 330.0), (2048.0, 500.0), (1024.0, 700.0), (1024.0, 950.0)]
+
+
+def serve_bench(ctx, n_req, load, seed=77):
+    """Poisson stream of (band, sky patch, spin-down range) requests through the
+    continuous-batching server; bands are resident 1 Hz peakmaps of a ~149 d
+    run with T_FFT chosen by band."""
+    import numpy as np
+    import torch
+
+    from paper_1407_8333_amd import api, synth
+    rng = synth.rng_for(seed)
+    t_obs = 149.0 * 86400.0
+    bands = []
+    for k, (t_fft, f_lo) in enumerate(SERVE_BANDS):
+        n_fft = int(round(t_obs / (0.5 * t_fft)))
+        m = synth.band_margin_bins(f_lo + 1, t_fft, n_fft, 1e-8)
+        pm = synth.make_noise_peakmap(n_fft, t_fft, int(f_lo * t_fft) - m, int((f_lo + 1) * t_fft) + m,
+                                      seed=seed + k)
+        bands.append((pm, f_lo, ctx.upload(pm)))
+    ranges = [(-1e-9, 1e-10), (-1e-8, 1e-9)]
+
+    def draw():
+        pm, f_lo, dpm = bands[int(rng.integers(len(bands)))]
+        grid = synth.make_grid(pm, f_lo, f_lo + 1.0, *ranges[int(rng.integers(2))])
+        sel = synth.Selection(width=int(round(0.1 * grid.kf * pm.t_fft)))
+        sky = synth.sky_uniform(int(rng.integers(1, 257)), rng)
+        return dpm, grid, sel, sky
+
+    srv = api.Server(ctx, hbm_budget=48 << 30, lanes=4)
+    # capacity: a burst of requests submitted at once
+    burst = [draw() for _ in range(12)]
+    outs = [torch.empty((len(b[3]), api.n_subbands(b[1], b[2]), 2, 8), dtype=torch.int32,
+                        device="cuda") for b in burst]
+    for b, o in zip(burst, outs):  # first use of each shape: tile autotuning, allocation
+        api.fh_hough_candidates(ctx, b[0], b[3], b[1], b[2], out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, o in zip(burst, outs):
+        srv.submit(b[0], b[3], b[1], b[2], o)
+    got = 0
+    while got < len(burst):
+        got += len(srv.poll())
+    cap = len(burst) / (time.perf_counter() - t0)
+    rate = load * cap
+    reqs = [draw() for _ in range(n_req)]
+    outs = [torch.empty((len(r[3]), api.n_subbands(r[1], r[2]), 2, 8), dtype=torch.int32,
+                        device="cuda") for r in reqs]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    done = []
+    t0 = time.perf_counter()
+    k = 0
+    while len(done) < n_req:
+        now = time.perf_counter() - t0
+        while k < n_req and arrivals[k] <= now:
+            r = reqs[k]
+            srv.submit(r[0], r[3], r[1], r[2], outs[k], tag=k)
+            k += 1
+        done.extend(srv.poll())
+    wall = time.perf_counter() - t0
+    srv.close()
+    for _, _, d in bands:
+        d.release()
+    lat = [c["latency_ms"] for c in done]
+    cells = sum(c["cell_updates"] for c in done)
+    return {"requests": n_req, "lanes": 4, "hbm_budget_gib": 48,
+            "arrival_rate_per_s": rate, "capacity_per_s": cap, "load": load,
+            "p50_latency_ms": pct(lat, 50), "p99_latency_ms": pct(lat, 99),
+            "mean_queue_ms": float(np.mean([c["queue_ms"] for c in done])),
+            "throughput": cells / wall, "unit": "cell-updates/s",
+            "bands": ["T_FFT %d s at %g-%g Hz" % (t, f, f + 1) for t, f in SERVE_BANDS],
+            "sky_patch": "1-256 random directions", "spin_down_ranges": ranges}
 
 
 def main():
@@ -204,6 +283,8 @@ def main():
                      "kernel": "k_tiles_persistent (one op = one ds_add_u32 cell update)",
                      "launch_ms": tiles_ms_avg, "cells_per_launch": cells_per_launch},
     }
+    if args.serve_requests > 0:
+        res["serving"] = serve_bench(ctx, args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
     dpm.release()

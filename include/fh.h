@@ -150,6 +150,12 @@ void fh_ctx_destroy(fh_ctx *ctx);
  * is not finite or outside (0, 65536). */
 fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
 
+/* Tuning knobs of a context, for experiments and tests.  Results never
+ * depend on them.  Names: "window_method" (0 = two binary searches per peak
+ * window, 1 = one sweep per FFT, default 1).  FH_E_INVALID for an unknown
+ * name or value. */
+fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value);
+
 /* ---- peakmaps ---------------------------------------------------------- */
 
 /* Validate a host peakmap and copy it to device memory owned by the returned
@@ -158,6 +164,26 @@ fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
  * or velocities, |v| >= 1e-2, T_FFT <= 0. */
 fh_status fh_peakmap_upload(fh_ctx *ctx, const fh_peakmap_desc *desc, void *stream,
                             fh_peakmap **out);
+
+/* Build a device-resident peakmap from equalised spectra (Sec. "Peakmap",
+ * Eq. pm): per FFT i and row bin j, R = d_sp[i][j] / d_sar[i][j] (float32,
+ * correctly rounded; d_sar = NULL means d_sp already holds R); bin j
+ * (1 <= j <= n_bins - 2; the first and last bins of a row are guards) is a
+ * peak of natural bin k0 + j when R > theta and R is strictly larger than
+ * both neighbours.  d_sp / d_sar: device [n_fft][ld] float32, ld >= n_bins.
+ * t, v, t_fft: host arrays as in fh_peakmap_desc.  Synchronises `stream`
+ * (the peak count sizes the result). */
+fh_status fh_peakmap_from_spectra(fh_ctx *ctx, int32_t n_fft, int32_t n_bins, int64_t ld,
+                                  const float *d_sp, const float *d_sar, int32_t k0, float theta,
+                                  const double *t, const double *v, double t_fft, void *stream,
+                                  fh_peakmap **out);
+
+/* Copy a peakmap's CSR back to host arrays: offsets [n_fft+1] and bins
+ * [n_peaks] (either may be NULL).  Synchronous. */
+fh_status fh_peakmap_download(fh_ctx *ctx, const fh_peakmap *pm, int64_t *offsets, int32_t *bins);
+
+/* Number of FFTs and peaks of a peakmap. */
+fh_status fh_peakmap_shape(const fh_peakmap *pm, int32_t *n_fft, int64_t *n_peaks);
 
 /* Free a peakmap's device memory (after work using it has completed). */
 void fh_peakmap_release(fh_ctx *ctx, fh_peakmap *pm);

@@ -89,8 +89,13 @@ _PROTOS = {
     "fh_ctx_create": ([ctypes.c_int32, ctypes.POINTER(P)], ctypes.c_int),
     "fh_ctx_destroy": ([P], None),
     "fh_ctx_check": ([P, P], ctypes.c_int),
+    "fh_ctx_set_option": ([P, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
     "fh_peakmap_upload": ([P, ctypes.POINTER(fh_peakmap_desc), P, ctypes.POINTER(P)], ctypes.c_int),
     "fh_peakmap_release": ([P, P], None),
+    "fh_peakmap_from_spectra": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, ctypes.c_int32,
+                                 ctypes.c_float, P, P, ctypes.c_double, P, ctypes.POINTER(P)], ctypes.c_int),
+    "fh_peakmap_download": ([P, P, P, P], ctypes.c_int),
+    "fh_peakmap_shape": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "fh_peakmap_bytes": ([P], ctypes.c_int64),
     "fh_plan_query": ([P, P, ctypes.POINTER(fh_grid), ctypes.c_int32,
                        ctypes.POINTER(fh_plan_info)], ctypes.c_int),
@@ -173,3 +178,7 @@ fh_server_poll = _fwd("fh_server_poll")
 fh_server_cancel = _fwd("fh_server_cancel")
 fh_server_stats = _fwd("fh_server_stats")
 fh_server_destroy = _fwd("fh_server_destroy")
+fh_ctx_set_option = _fwd("fh_ctx_set_option")
+fh_peakmap_from_spectra = _fwd("fh_peakmap_from_spectra")
+fh_peakmap_download = _fwd("fh_peakmap_download")
+fh_peakmap_shape = _fwd("fh_peakmap_shape")

@@ -63,6 +63,9 @@ class Context:
     def check(self, stream=None):
         check(_lib.fh_ctx_check(self.handle, _stream(stream)))
 
+    def set_option(self, name: str, value: int):
+        check(_lib.fh_ctx_set_option(self.handle, name.encode(), int(value)))
+
     def profile(self, enable: bool):
         check(_lib.fh_ctx_profile(self.handle, 1 if enable else 0))
 
@@ -98,6 +101,37 @@ class DevicePeakmap:
         h = ctypes.c_void_p()
         check(_lib.fh_peakmap_upload(ctx.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self.handle = h
+
+    @classmethod
+    def from_spectra(cls, ctx: Context, sp: torch.Tensor, k0: int, theta: float, t, v, t_fft: float,
+                     sar: Optional[torch.Tensor] = None, stream=None) -> "DevicePeakmap":
+        """Peakmap of equalised spectra R = sp / sar (Eq. pm) built on the GPU.
+        sp, sar: device float32 [n_fft, n_bins]; row bin j is natural bin k0 + j."""
+        assert sp.dtype == torch.float32 and sp.is_cuda and sp.dim() == 2 and sp.stride(1) == 1
+        if sar is not None:
+            assert sar.shape == sp.shape and sar.dtype == torch.float32 and sar.stride() == sp.stride()
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        check(_lib.fh_peakmap_from_spectra(ctx.handle, sp.shape[0], sp.shape[1], sp.stride(0),
+                                           ctypes.c_void_p(sp.data_ptr()),
+                                           None if sar is None else ctypes.c_void_p(sar.data_ptr()),
+                                           int(k0), float(theta), t.ctypes.data, v.ctypes.data,
+                                           float(t_fft), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        n, p = ctypes.c_int32(), ctypes.c_int64()
+        check(_lib.fh_peakmap_shape(h, ctypes.byref(n), ctypes.byref(p)))
+        self.n_fft, self.n_peaks = n.value, p.value
+        return self
+
+    def download(self):
+        """(offsets int64 [N+1], bins int32 [P]) on the host."""
+        off = np.zeros(self.n_fft + 1, np.int64)
+        bins = np.zeros(max(1, self.n_peaks), np.int32)
+        check(_lib.fh_peakmap_download(self.ctx.handle, self.handle, off.ctypes.data, bins.ctypes.data))
+        return off, bins[: self.n_peaks]
 
     @property
     def nbytes(self) -> int:

@@ -22,6 +22,13 @@ constexpr int kLdsBytes = 163840;
 constexpr int kLdsReserve = 256;
 // Number of XCDs of an MI355X; workgroup w is dispatched to XCD w % 8.
 constexpr int kXcds = 8;
+// Stripe-edge entries appended after each FFT's peaks (a chunk of 16 peaks
+// may read up to 15 past a window's end).
+constexpr int kYPad = 16;
+// Stripe edges per sky direction: every peak plus kYPad per FFT.
+__host__ __device__ inline int64_t y_stride(int64_t n_peaks, int32_t n_fft) {
+    return n_peaks + (int64_t)kYPad * n_fft;
+}
 
 // Per-weight-vector statistics computed on the device.
 struct WeightStats {
@@ -65,15 +72,23 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
                        const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st);
+// method 0: two binary searches per entry; 1: one sweep per FFT
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
                           const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
-                          int32_t kf, int32_t n_slots, int2 *win, hipStream_t st);
+                          int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st);
 hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
                         bool persistent, int32_t n_tiles, int32_t grid_blocks, hipStream_t st);
 hipError_t launch_select(const unsigned long long *colmax, int32_t nf, int32_t n_slots,
                          const fh_select &sel, int32_t sky_base, int32_t n_fft,
                          const WeightStats *ws, int32_t ws_stride, fh_candidate *out,
                          hipStream_t st);
+// peakmap construction from equalised spectra
+hipError_t launch_pm_rows(int32_t n_fft, int32_t n_bins, int64_t ld, const float *sp, const float *sar,
+                          int32_t k0, float theta, int32_t cap, int32_t *scratch, int32_t *counts,
+                          hipStream_t st);
+hipError_t launch_pm_scan(int32_t n_fft, const int32_t *counts, int64_t *offsets, hipStream_t st);
+hipError_t launch_pm_pack(int32_t n_fft, int32_t cap, const int32_t *scratch, const int64_t *offsets,
+                          int32_t *bins, hipStream_t st);
 int tile_lds_bytes(int W, int kf);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).
 hipError_t init_kernel_attributes();

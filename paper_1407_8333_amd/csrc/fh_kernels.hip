@@ -36,6 +36,10 @@ constexpr int64_t kOne32 = (int64_t)1 << 32;
 
 __device__ __forceinline__ int64_t shr32(int64_t a) { return a >> 32; }  // floor(a / 2^32)
 
+// Stripe edge stored after each FFT's peaks (kYPad copies): far beyond every
+// tile, so a read past a window's end never adds inside a tile.
+constexpr int64_t kYSentinel = (int64_t)1 << 61;
+
 // ----------------------------------------------------------------------------
 // fills (graph-safe replacements for memset)
 
@@ -145,13 +149,16 @@ __global__ void __launch_bounds__(256) k_prep(
     d = 1.0 + d;
     const double r = 1.0 / d;
     const int64_t c = -b0 * kOne32 - (int64_t)kf * (kOne32 / 2) - g0[i] + (kOne32 - 1);
-    int64_t *Ys = Y + (int64_t)slot * n_peaks;
+    // FFT i's edges start at offsets[i] + kYPad * i and are followed by kYPad
+    // sentinels
+    int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
     const int64_t e = offsets[i + 1];
     for (int64_t p = offsets[i] + lane; p < e; p += 64) {
         double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
         x = x * kTwo32;
         Ys[p] = (int64_t)floor(x) + c;
     }
+    if (lane < kYPad) Ys[e + lane] = kYSentinel;
     if (w != nullptr && lane == 0) {
         const WeightStats st = ws[(int64_t)slot * ws_stride];
         double wi = (double)w[(int64_t)slot * w_stride + i];
@@ -182,8 +189,8 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
     const int64_t wc = (int64_t)W + kf - 1;
     const int64_t q_lo = (int64_t)s_lo * dg[i] + c0 * kOne32;
     const int64_t q_hi = (int64_t)s_hi * dg[i] + c0 * kOne32;
-    const int64_t *Ys = Y + (int64_t)slot * n_peaks;
-    const int64_t p0 = offsets[i], p1 = offsets[i + 1];
+    const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
+    const int64_t p0 = offsets[i] + (int64_t)kYPad * i, p1 = offsets[i + 1] + (int64_t)kYPad * i;
     // lo: first peak whose larger column is >= 0
     int64_t a = p0, b = p1;
     while (a < b) {
@@ -204,6 +211,69 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
         if (cmin >= wc) b = m; else a = m + 1;
     }
     win[(((int64_t)slot * nrbg + g) * nbb + jb) * n_fft + i] = make_int2((int)lo, (int)a);
+}
+
+// Same windows by one sweep over each FFT's peaks (one wave per FFT, every
+// row group): with jhi(p) / jlo(p) the last / first bin block that peak p
+// reaches over a group's rows (non-decreasing in p),
+//   lo[jb] = first p with jhi(p) >= jb,   hi[jb] = first p with jlo(p) > jb,
+// and each lane writes the entries whose boundary falls on its peak.
+
+__device__ __forceinline__ int floor_div_w(int64_t x, int W, float inv_w) {
+    int q = (int)floorf((float)x * inv_w);
+    if ((int64_t)q * W > x) --q;
+    else if ((int64_t)(q + 1) * W <= x) ++q;
+    return q;
+}
+
+__global__ void __launch_bounds__(256) k_windows_sweep(
+    int32_t n_fft, const int64_t *__restrict__ offsets, const int64_t *__restrict__ Y,
+    int64_t n_peaks, const int64_t *__restrict__ dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+    int32_t kf, int2 *__restrict__ win) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int slot = blockIdx.y;
+    if (i >= n_fft) return;
+    const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
+    const int p0 = (int)(offsets[i] + (int64_t)kYPad * i);
+    const int p1 = (int)(offsets[i + 1] + (int64_t)kYPad * i);
+    const int64_t dG = dg[i];
+    const float inv_w = 1.0f / (float)W;
+    for (int g = 0; g < nrbg; ++g) {
+        int2 *wg = win + ((int64_t)slot * nrbg + g) * nbb * (int64_t)n_fft + i;
+        const int s_lo = g * kRowBlocksPerGroup * kTileRows;
+        const int s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
+        const int64_t q_lo = (int64_t)s_lo * dG, q_hi = (int64_t)s_hi * dG;
+        int prev_hi = -1;  // jhi of the peak before this chunk
+        int prev_lo = 0;   // jlo of the peak before this chunk
+        for (int pb = p0; pb < p1; pb += 64) {
+            const int p = pb + lane;
+            int jhi = nbb - 1, jlo = nbb;  // past the segment end
+            if (p < p1) {
+                const int64_t y = Ys[p];
+                const int64_t a1 = shr32(y - q_lo), a2 = shr32(y - q_hi);
+                const int64_t amin = a1 < a2 ? a1 : a2, amax = a1 < a2 ? a2 : a1;
+                jhi = max(-1, min(nbb - 1, floor_div_w(amax + kf - 1, W, inv_w)));
+                jlo = max(0, min(nbb, floor_div_w(amin, W, inv_w)));
+            }
+            int before_hi = __shfl_up(jhi, 1);
+            int before_lo = __shfl_up(jlo, 1);
+            if (lane == 0) {
+                before_hi = prev_hi;
+                before_lo = prev_lo;
+            }
+            if (p < p1) {
+                for (int jb = before_hi + 1; jb <= jhi; ++jb) wg[(int64_t)jb * n_fft].x = p;
+                for (int jb = before_lo; jb < jlo; ++jb) wg[(int64_t)jb * n_fft].y = p;
+            }
+            const int last = min(63, p1 - 1 - pb);
+            prev_hi = __shfl(jhi, last);
+            prev_lo = __shfl(jlo, last);
+        }
+        // bin blocks past the last peak's reach end at the segment end
+        for (int jb = prev_hi + 1 + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_fft].x = p1;
+        for (int jb = prev_lo + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_fft].y = p1;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -250,7 +320,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const int64_t c0 = (int64_t)jb * W - (kf - 1);
     const int g = rb / kRowBlocksPerGroup;
     const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * A.n_fft;
-    const int64_t *__restrict__ Ys = A.Y + (int64_t)slot * A.n_peaks;
+    const int64_t *__restrict__ Ys = A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft);
     const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
     const uint32_t dump = (uint32_t)wc;
     const uint32_t lane_off = (uint32_t)j;
@@ -314,24 +384,16 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
 #pragma unroll
             for (int u = 0; u < kChunkIters; ++u) buf[u] = bp[4 * u];
         };
+        // Peaks past a window's end (up to 15, inside the FFT's padded run)
+        // either miss the tile or are sentinels: both land in the dump column.
         auto accumulate = [&](const int64_t (&buf)[kChunkIters], const Pos &c, int64_t nq,
                               uint32_t val) {
             const int cnt = c.hi - c.p0;
-            if (cnt >= 4 * kChunkIters) {
 #pragma unroll
-                for (int u = 0; u < kChunkIters; ++u) {
+            for (int u = 0; u < kChunkIters; ++u) {
+                if (u == 0 || 4 * u < cnt) {
                     const uint32_t col = (uint32_t)(int32_t)shr32(buf[u] + nq);
                     const uint32_t cu = col < dump ? col : dump;
-                    atomicAdd(lds + cu * kTileRows + lane_off, val);
-                }
-            } else {
-                // partial chunk: lanes past the window end add to the dump
-                // column (every loaded register is consumed on every path)
-#pragma unroll
-                for (int u = 0; u < kChunkIters; ++u) {
-                    const uint32_t col = (uint32_t)(int32_t)shr32(buf[u] + nq);
-                    uint32_t cu = col < dump ? col : dump;
-                    cu = 4 * u + grp < cnt ? cu : dump;
                     atomicAdd(lds + cu * kTileRows + lane_off, val);
                 }
             }
@@ -573,6 +635,92 @@ __global__ void __launch_bounds__(256) k_select(const unsigned long long *__rest
     }
 }
 
+// ----------------------------------------------------------------------------
+// peakmap construction (Sec. "Peakmap", Eq. pm): R = S_P / S_AR bin by bin; a
+// peak is a bin above theta that is strictly larger than both neighbours.
+// One workgroup per FFT writes its peaks compactly into a per-FFT scratch run
+// (at most one peak in every two bins) and its count; after a scan of the
+// counts a second kernel packs the runs into the CSR.
+
+__global__ void __launch_bounds__(256) k_pm_rows(int32_t n_bins, int64_t ld,
+                                                 const float *__restrict__ sp,
+                                                 const float *__restrict__ sar, int32_t k0,
+                                                 float theta, int32_t cap,
+                                                 int32_t *__restrict__ scratch,
+                                                 int32_t *__restrict__ counts) {
+    __shared__ int wsum[4];
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float *P = sp + (int64_t)i * ld;
+    const float *A = sar ? sar + (int64_t)i * ld : nullptr;
+    int32_t *out = scratch + (int64_t)i * cap;
+    int base = 0;
+    for (int j0 = 1; j0 < n_bins - 1; j0 += blockDim.x) {
+        const int j = j0 + threadIdx.x;
+        bool pk = false;
+        if (j < n_bins - 1) {
+            float l = P[j - 1], c = P[j], r = P[j + 1];
+            if (A) {
+                l = l / A[j - 1];
+                c = c / A[j];
+                r = r / A[j + 1];
+            }
+            pk = c > theta && c > l && c > r;
+        }
+        const uint64_t m = __ballot(pk);
+        if (lane == 0) wsum[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        if (pk) {
+            const int pos = base + before + __popcll(m & ((1ull << lane) - 1ull));
+            out[pos] = k0 + j;
+        }
+        base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[i] = base;
+}
+
+// exclusive scan of per-FFT counts into CSR offsets (one workgroup)
+__global__ void __launch_bounds__(1024) k_pm_scan(int32_t n, const int32_t *__restrict__ counts,
+                                                  int64_t *__restrict__ offsets) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b = 0; b < n; b += blockDim.x) {
+        const int i = b + threadIdx.x;
+        const int64_t v = i < n ? counts[i] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+            const int64_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) offsets[i] = carry + part[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry += part[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offsets[n] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_pm_pack(int32_t cap, const int32_t *__restrict__ scratch,
+                                                 const int64_t *__restrict__ offsets,
+                                                 int32_t *__restrict__ bins) {
+    const int i = blockIdx.x;
+    const int64_t o = offsets[i];
+    const int c = (int)(offsets[i + 1] - o);
+    const int32_t *src = scratch + (int64_t)i * cap;
+    for (int t = threadIdx.x; t < c; t += blockDim.x) bins[o + t] = src[t];
+}
+
 inline unsigned grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g > 65535 * 16) g = 65535 * 16;
@@ -626,9 +774,14 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
 
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
                           const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
-                          int32_t kf, int32_t n_slots, int2 *win, hipStream_t st) {
-    dim3 grid(grid_for((int64_t)nbb * n_fft, 256), nrbg, n_slots);
-    k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+                          int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st) {
+    if (method == 0) {
+        dim3 grid(grid_for((int64_t)nbb * n_fft, 256), nrbg, n_slots);
+        k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+    } else {
+        dim3 grid((n_fft + 3) / 4, n_slots);
+        k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+    }
     return hipGetLastError();
 }
 
@@ -683,6 +836,24 @@ hipError_t launch_select(const unsigned long long *colmax, int32_t nf, int32_t n
     const int n_sb = (nf + sel.width - 1) / sel.width;
     dim3 grid(n_sb, n_slots);
     k_select<<<grid, 256, 0, st>>>(colmax, nf, sel, sky_base, n_fft, ws, ws_stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_rows(int32_t n_fft, int32_t n_bins, int64_t ld, const float *sp, const float *sar,
+                          int32_t k0, float theta, int32_t cap, int32_t *scratch, int32_t *counts,
+                          hipStream_t st) {
+    k_pm_rows<<<n_fft, 256, 0, st>>>(n_bins, ld, sp, sar, k0, theta, cap, scratch, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_scan(int32_t n_fft, const int32_t *counts, int64_t *offsets, hipStream_t st) {
+    k_pm_scan<<<1, 1024, 0, st>>>(n_fft, counts, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_pack(int32_t n_fft, int32_t cap, const int32_t *scratch, const int64_t *offsets,
+                          int32_t *bins, hipStream_t st) {
+    k_pm_pack<<<n_fft, 256, 0, st>>>(cap, scratch, offsets, bins);
     return hipGetLastError();
 }
 

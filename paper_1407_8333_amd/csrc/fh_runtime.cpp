@@ -141,6 +141,7 @@ struct fh_ctx {
     int32_t n_cu = 256;
     Workspace main_ws;
     Workspace *cur = &main_ws;  // workspace used by the launch sequences
+    int32_t window_method = 1;  // peak windows: 0 binary searches, 1 sweep
     DevBuf err;
     // autotuned tile width per problem shape
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
@@ -279,8 +280,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     fh_status s;
     if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
-    // the tile kernels read up to 15 stripe edges past a window's end
-    if ((s = ctx->cur->Y.ensure((size_t)8 * (std::max<int64_t>(1, pm->n_peaks) * slots + 16), st))) return s;
+    if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
     if ((s = ctx->cur->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
@@ -357,7 +357,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
                        g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
-                          p.W, g->kf, slots, b.win, st));
+                          p.W, g->kf, slots, b.win, ctx->window_method, st));
     return FH_OK;
 }
 
@@ -421,7 +421,7 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
 // more tiles per persistent launch)
 int default_chunk(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
     if (requested > 0) return requested;
-    const int64_t per_sky = 8 * pm->n_peaks + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft + 8 * (int64_t)g->nf;
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft + 8 * (int64_t)g->nf;
     const int64_t by_mem = std::max<int64_t>(1, ((int64_t)3 << 30) / std::max<int64_t>(1, per_sky));
     return (int)std::min<int64_t>(by_mem, 256);
 }
@@ -567,6 +567,18 @@ void fh_ctx_destroy(fh_ctx *ctx) {
     delete ctx;
 }
 
+fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!name) return fail(FH_E_INVALID, "option name is NULL");
+    if (std::strcmp(name, "window_method") == 0) {
+        if (value != 0 && value != 1) return fail(FH_E_INVALID, "window_method must be 0 or 1");
+        ctx->window_method = (int32_t)value;
+        return FH_OK;
+    }
+    return fail(FH_E_INVALID, "unknown option '%s'", name);
+}
+
 fh_status fh_ctx_check(fh_ctx *ctx, void *stream) {
     fh_status s;
     if ((s = check_ctx(ctx))) return s;
@@ -654,6 +666,96 @@ fh_status fh_peakmap_upload(fh_ctx *ctx, const fh_peakmap_desc *d, void *stream,
     return FH_OK;
 }
 
+fh_status fh_peakmap_from_spectra(fh_ctx *ctx, int32_t n_fft, int32_t n_bins, int64_t ld,
+                                  const float *d_sp, const float *d_sar, int32_t k0, float theta,
+                                  const double *t, const double *v, double t_fft, void *stream,
+                                  fh_peakmap **out) {
+    fh_status s;
+    if (!out) return fail(FH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((s = check_ctx(ctx))) return s;
+    if (n_fft < 1 || n_fft > (1 << 24)) return fail(FH_E_INVALID, "n_fft=%d outside 1..2^24", n_fft);
+    if (n_bins < 3 || ld < n_bins) return fail(FH_E_INVALID, "need n_bins >= 3 and ld >= n_bins");
+    if (!d_sp || !t || !v) return fail(FH_E_INVALID, "a spectrum or time/velocity array is NULL");
+    if (k0 < 0 || (int64_t)k0 + n_bins >= ((int64_t)1 << 31)) return fail(FH_E_INVALID, "k0 out of range");
+    if (!std::isfinite(theta)) return fail(FH_E_INVALID, "theta is not finite");
+    if (!(t_fft > 0) || !std::isfinite(t_fft)) return fail(FH_E_INVALID, "t_fft must be finite and > 0");
+    fh_peakmap *pm = new fh_peakmap();
+    pm->n_fft = n_fft;
+    pm->t_fft = t_fft;
+    pm->t_min = pm->t_max = t[0];
+    for (int32_t i = 0; i < n_fft; ++i) {
+        if (!std::isfinite(t[i])) { delete pm; return fail(FH_E_INVALID, "t[%d] is not finite", i); }
+        pm->t_min = std::min(pm->t_min, t[i]);
+        pm->t_max = std::max(pm->t_max, t[i]);
+        const double *vi = v + 3 * (int64_t)i;
+        if (!std::isfinite(vi[0]) || !std::isfinite(vi[1]) || !std::isfinite(vi[2])) {
+            delete pm;
+            return fail(FH_E_INVALID, "v[%d] is not finite", i);
+        }
+        const double vn = std::sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+        if (vn >= 1e-2) { delete pm; return fail(FH_E_INVALID, "|v[%d]| = %g >= 1e-2", i, vn); }
+        pm->v_max = std::max(pm->v_max, vn);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t cap = n_bins / 2 + 1;  // strict local maxima are never adjacent
+    int32_t *scratch = nullptr, *counts = nullptr;
+    const size_t b_off = 8 * (size_t)(n_fft + 1), b_t = 8 * (size_t)n_fft, b_v = 24 * (size_t)n_fft;
+    if (hipMalloc(&scratch, 4 * (size_t)n_fft * cap) != hipSuccess || hipMalloc(&counts, 4 * (size_t)n_fft) != hipSuccess ||
+        hipMalloc(&pm->d_offsets, b_off) != hipSuccess || hipMalloc(&pm->d_t, b_t) != hipSuccess ||
+        hipMalloc(&pm->d_v, b_v) != hipSuccess) {
+        if (scratch) hipFree(scratch);
+        if (counts) hipFree(counts);
+        fh_peakmap_release(ctx, pm);
+        return fail(FH_E_NOMEM, "device allocation for the peakmap failed");
+    }
+    std::vector<int64_t> h_off(n_fft + 1);
+    hipError_t e = launch_pm_rows(n_fft, n_bins, ld, d_sp, d_sar, k0, theta, cap, scratch, counts, st);
+    if (e == hipSuccess) e = launch_pm_scan(n_fft, counts, pm->d_offsets, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_off.data(), pm->d_offsets, b_off, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const int64_t P = e == hipSuccess ? h_off[n_fft] : 0;
+    if (e == hipSuccess && hipMalloc(&pm->d_bins, 4 * (size_t)std::max<int64_t>(1, P)) != hipSuccess)
+        e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = launch_pm_pack(n_fft, cap, scratch, pm->d_offsets, pm->d_bins, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(pm->d_t, t, b_t, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(pm->d_v, v, b_v, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(scratch);
+    hipFree(counts);
+    if (e != hipSuccess) {
+        fh_peakmap_release(ctx, pm);
+        return fail(e == hipErrorOutOfMemory ? FH_E_NOMEM : FH_E_DEVICE, "peakmap construction failed: %s",
+                    hipGetErrorString(e));
+    }
+    pm->n_peaks = P;
+    pm->k_min = k0 + 1;
+    pm->k_max = k0 + n_bins - 2;
+    pm->adjacent = 0;
+    for (int32_t i = 0; i < n_fft; ++i)
+        pm->max_per_fft = std::max<int32_t>(pm->max_per_fft, (int32_t)(h_off[i + 1] - h_off[i]));
+    pm->bytes = (int64_t)(b_off + 4 * (size_t)std::max<int64_t>(1, P) + b_t + b_v);
+    *out = pm;
+    return FH_OK;
+}
+
+fh_status fh_peakmap_download(fh_ctx *ctx, const fh_peakmap *pm, int64_t *offsets, int32_t *bins) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if (offsets) HIP_OK(hipMemcpy(offsets, pm->d_offsets, 8 * (size_t)(pm->n_fft + 1), hipMemcpyDeviceToHost));
+    if (bins && pm->n_peaks > 0)
+        HIP_OK(hipMemcpy(bins, pm->d_bins, 4 * (size_t)pm->n_peaks, hipMemcpyDeviceToHost));
+    return FH_OK;
+}
+
+fh_status fh_peakmap_shape(const fh_peakmap *pm, int32_t *n_fft, int64_t *n_peaks) {
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if (n_fft) *n_fft = pm->n_fft;
+    if (n_peaks) *n_peaks = pm->n_peaks;
+    return FH_OK;
+}
+
 void fh_peakmap_release(fh_ctx *ctx, fh_peakmap *pm) {
     if (!pm) return;
     if (ctx) hipSetDevice(ctx->device);
@@ -678,7 +780,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->tile_bins = p.W;
     out->n_row_blocks = p.nrb;
     out->n_bin_blocks = p.nbb;
-    out->workspace_bytes = 8 * (int64_t)pm->n_peaks + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft +
+    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
@@ -850,7 +952,7 @@ struct Lane {
 // Workspace bytes of one search of `chunk` directions with plan p.
 int64_t search_footprint(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk, int n_sky) {
     const int64_t N = pm->n_fft;
-    const int64_t per_sky = 8 * std::max<int64_t>(1, pm->n_peaks) + 8 * (int64_t)p.nrbg * p.nbb * N +
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * N +
                             8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
     return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
 }
