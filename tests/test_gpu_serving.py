@@ -57,13 +57,14 @@ def test_alone_equals_mix(setup):
     torch.cuda.synchronize()
     srv = api.Server(ctx, hbm_budget=1 << 30, lanes=3)
     outs, ids = [], []
+    done = {}
     for k, (bi, grid, sel, sky, weighted) in enumerate(reqs):
         out = torch.full((len(sky), api.n_subbands(grid, sel), 2, 8), -7, dtype=torch.int32, device="cuda")
         outs.append(out)
         ids.append(srv.submit(dpms[bi], sky, grid, sel, out, weights=wts[bi] if weighted else None, tag=k))
         if k % 3 == 2:  # requests keep arriving while others run
-            srv.poll()
-    done = {}
+            for c in srv.poll():
+                done[c["tag"]] = c
     for _ in range(100000):
         for c in srv.poll():
             done[c["tag"]] = c
