@@ -22,12 +22,13 @@ constexpr int kLdsBytes = 163840;
 constexpr int kLdsReserve = 256;
 // Number of XCDs of an MI355X; workgroup w is dispatched to XCD w % 8.
 constexpr int kXcds = 8;
-// Stripe-edge entries appended after each FFT's peaks (a chunk of 16 peaks
-// may read up to 15 past a window's end).
+// Sentinel stripe edges appended after each FFT's peaks: a block read may
+// run up to 3 peaks past a window's end into accumulated steps.
 constexpr int kYPad = 16;
-// Stripe edges per sky direction: every peak plus kYPad per FFT.
+// Stripe edges per sky direction: every peak plus kYPad per FFT, plus one
+// block of slack at the end (a block load reads up to 63 past a window start).
 __host__ __device__ inline int64_t y_stride(int64_t n_peaks, int32_t n_fft) {
-    return n_peaks + (int64_t)kYPad * n_fft;
+    return n_peaks + (int64_t)kYPad * n_fft + 64;
 }
 
 // Per-weight-vector statistics computed on the device.
@@ -48,6 +49,8 @@ struct TileArgs {
     const int64_t *Y;             // [slot][P] stripe edges (Q32.32, see prep kernel)
     const int2 *win;              // [slot][nrbg][nbb][N] peak windows
     const int64_t *dg;            // [N] row step of the stripe edge (Q32.32)
+    const int64_t *rowsh;         // [N][ns_pad] -s * dG_i
+    int32_t ns_pad;               // rows of all row blocks (nrb * 16)
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
     const WeightStats *ws;        // [slot * ws_stride] or nullptr
     int32_t ws_stride;            // 0: one shared weight vector, 1: one per slot
@@ -66,6 +69,8 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st);
+hipError_t launch_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *dg, int64_t *rowsh,
+                             hipStream_t st);
 hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
                                int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st);
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,

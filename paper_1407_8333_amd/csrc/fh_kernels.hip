@@ -73,6 +73,16 @@ __global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, dou
     dg[i] = (int64_t)rint(b);
 }
 
+// Row shifts of the stripe edge: T[i][s] = -s * dG_i, s < ns_pad (the rows
+// of every tile, including the padding rows of the last row block).
+__global__ void k_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *__restrict__ dg,
+                             int64_t *__restrict__ rowsh) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (s >= ns_pad || i >= n_fft) return;
+    rowsh[(int64_t)i * ns_pad + s] = -((int64_t)s * dg[i]);
+}
+
 // ----------------------------------------------------------------------------
 // weight statistics and fixed-point scale (Eq. ncountadap)
 
@@ -291,8 +301,27 @@ __device__ __forceinline__ T ld_scalar(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
 }
 
-// Peaks handled per lane group and chunk (4 groups -> 16 peaks per chunk).
-constexpr int kChunkIters = 4;
+// One step of the accumulation: lane (group g, row j) adds the stripe of
+// peak 4u + g of the current block, whose edge sits in lane (g, u) and is
+// broadcast to the 16 lanes of the group with DPP row_newbcast:u.  The edge
+// is already relative to the tile's first column, so
+//   col = floor((Y' - s dG) / 2^32)  is the tile column of the stripe start,
+// and every column outside [0, W + K_f - 1) (negative ones wrap to large
+// unsigned values) goes to the dump column.
+template <int U>
+__device__ __forceinline__ void stripe_step(uint32_t ylo, uint32_t yhi, uint64_t t, uint32_t dump,
+                                            uint32_t lane_off, uint32_t val,
+                                            uint32_t *__restrict__ lds) {
+    const uint32_t blo = __builtin_amdgcn_update_dpp(0u, ylo, 0x150 + U, 0xF, 0xF, true);
+    const uint32_t bhi = __builtin_amdgcn_update_dpp(0u, yhi, 0x150 + U, 0xF, 0xF, true);
+    const uint64_t sum = (((uint64_t)bhi << 32) | blo) + t;
+    const uint32_t col = (uint32_t)(sum >> 32);
+    const uint32_t cu = col < dump ? col : dump;
+    atomicAdd(lds + cu * kTileRows + lane_off, val);
+}
+
+// Peaks of one FFT handled per block (4 lane groups x 16 steps).
+constexpr int kBlock = 64;
 
 template <bool WEIGHTED, bool MAP, bool COLMAX>
 __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, int jb,
@@ -305,6 +334,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const int grp = lane >> 4;
     const int W = A.W, kf = A.kf;
     const int wc = W + kf - 1;
+    // LDS column c holds fine bin c0 + c, c in [0, wc); column wc is the dump.
     const int nwords = kTileRows * (wc + 1);
 
     for (int x = tid * 4; x < nwords; x += blockDim.x * 4) {
@@ -317,56 +347,41 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     __syncthreads();
 
     const int s0 = rb * kTileRows;
-    const int64_t c0 = (int64_t)jb * W - (kf - 1);
+    const int32_t c0 = jb * W - (kf - 1);
     const int g = rb / kRowBlocksPerGroup;
     const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * A.n_fft;
     const int64_t *__restrict__ Ys = A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft);
     const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
     const uint32_t dump = (uint32_t)wc;
     const uint32_t lane_off = (uint32_t)j;
+    const int lane_peak = 4 * j + grp;  // this lane's peak within a block
+    const int64_t *__restrict__ rowsh = A.rowsh + (s0 + j);
 
     // Each wave takes a contiguous run of FFTs, read 64 at a time (one per
-    // lane) into registers.  Its peaks are processed in chunks of 16 (four
-    // per 16-lane group) through two register buffers: the stripe edges of
-    // the next chunk are in flight while the current chunk is accumulated,
-    // across FFT boundaries.
+    // lane).  A block of up to 64 peaks of one FFT is loaded with one wave
+    // load (one edge per lane) together with the FFT's row shifts, while the
+    // previous block is accumulated.
     const int per = (A.n_fft + nwave - 1) / nwave;
     const int i_begin = wave * per;
     const int i_end = min(A.n_fft, i_begin + per);
-    const uint32_t jrow = (uint32_t)j;
 
+    struct Pos {
+        int k, p0, hi;
+        bool valid;
+    };
     for (int ib = i_begin; ib < i_end; ib += 64) {
         const int myi = ib + lane;
         int2 wl = make_int2(0, 0);
-        int64_t dl = 0;
         uint32_t vl = 1u;
         if (myi < i_end) {
             wl = win[myi];
-            dl = A.dg[myi];
             if (WEIGHTED) vl = wq[myi];
         }
         const uint64_t mask = __ballot(wl.x < wl.y);
         if (mask == 0) continue;
-
-        // -(row * dG + c0 * 2^32) for this lane's row, row = s0 + j:
-        // the wave-uniform part s0*dG + c0*2^32 on the scalar unit, plus j*dG.
-        auto edge_of = [&](int kk) {
-            const uint32_t dlo = __builtin_amdgcn_readlane((uint32_t)dl, kk);
-            const int32_t dhi = (int32_t)__builtin_amdgcn_readlane((uint32_t)((uint64_t)dl >> 32), kk);
-            const int64_t dG = (int64_t)(((uint64_t)(uint32_t)dhi << 32) | dlo);
-            const int64_t ndG = -dG;
-            const uint64_t base = (uint64_t)(-((int64_t)s0 * dG + c0 * kOne32));
-            const uint64_t lo = (uint64_t)jrow * (uint32_t)ndG + base;
-            const int32_t hi = __mul24((int)jrow, (int)(ndG >> 32));
-            return (int64_t)(lo + ((uint64_t)(uint32_t)hi << 32));
-        };
-        struct Pos {
-            int k, p0, hi;
-            bool valid;
-        };
         auto advance = [&](const Pos &c) {
             Pos n = c;
-            n.p0 = c.p0 + 4 * kChunkIters;
+            n.p0 = c.p0 + kBlock;
             if (n.p0 >= c.hi) {
                 const uint64_t rest = c.k >= 63 ? 0ull : mask & (~0ull << (c.k + 1));
                 if (rest == 0) {
@@ -379,64 +394,61 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             }
             return n;
         };
-        auto issue = [&](int64_t (&buf)[kChunkIters], const Pos &c) {
-            const int64_t *bp = Ys + c.p0 + grp;
-#pragma unroll
-            for (int u = 0; u < kChunkIters; ++u) buf[u] = bp[4 * u];
-        };
-        // Peaks past a window's end (up to 15, inside the FFT's padded run)
-        // either miss the tile or are sentinels: both land in the dump column.
-        auto accumulate = [&](const int64_t (&buf)[kChunkIters], const Pos &c, int64_t nq,
-                              uint32_t val) {
+        // stripe edge relative to the tile's first column c0
+        auto load_y = [&](const Pos &c) { return (uint64_t)Ys[c.p0 + lane_peak] - ((uint64_t)(uint32_t)c0 << 32); };
+        auto load_t = [&](const Pos &c) { return (uint64_t)rowsh[(int64_t)(ib + c.k) * A.ns_pad]; };
+        auto accumulate = [&](uint64_t y, uint64_t t, const Pos &c, uint32_t val) {
             const int cnt = c.hi - c.p0;
-#pragma unroll
-            for (int u = 0; u < kChunkIters; ++u) {
-                if (u == 0 || 4 * u < cnt) {
-                    const uint32_t col = (uint32_t)(int32_t)shr32(buf[u] + nq);
-                    const uint32_t cu = col < dump ? col : dump;
-                    atomicAdd(lds + cu * kTileRows + lane_off, val);
-                }
-            }
+            const uint32_t ylo = (uint32_t)y, yhi = (uint32_t)(y >> 32);
+#define FH_STEP(U)                                                                   \
+    if ((U) == 0 || 4 * (U) < cnt) stripe_step<U>(ylo, yhi, t, dump, lane_off, val, lds);
+            FH_STEP(0) FH_STEP(1) FH_STEP(2) FH_STEP(3) FH_STEP(4) FH_STEP(5) FH_STEP(6) FH_STEP(7)
+            FH_STEP(8) FH_STEP(9) FH_STEP(10) FH_STEP(11) FH_STEP(12) FH_STEP(13) FH_STEP(14) FH_STEP(15)
+#undef FH_STEP
         };
 
-        Pos pa;
-        pa.k = __builtin_ctzll(mask);
-        pa.p0 = __builtin_amdgcn_readlane(wl.x, pa.k);
-        pa.hi = __builtin_amdgcn_readlane(wl.y, pa.k);
-        pa.valid = true;
-        int64_t ya[kChunkIters], yb[kChunkIters];
-        issue(ya, pa);
-        int64_t nqa = edge_of(pa.k);
-        uint32_t va = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, pa.k) : 1u;
+        // Three blocks in flight: the loop body is unrolled over the three
+        // register slots, and every slot issues its loads on every path
+        // (re-reading the last valid block once the stream has ended) so the
+        // hardware wait counts stay exact.
+        Pos p0;
+        p0.k = __builtin_ctzll(mask);
+        p0.p0 = __builtin_amdgcn_readlane(wl.x, p0.k);
+        p0.hi = __builtin_amdgcn_readlane(wl.y, p0.k);
+        p0.valid = true;
+        auto next_of = [&](const Pos &c) {
+            Pos n = advance(c);
+            if (!c.valid) n.valid = false;
+            return n;
+        };
+        auto val_of = [&](const Pos &c) {
+            uint32_t v = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, c.k) : 1u;
+            asm volatile("" : "+v"(v));
+            return v;
+        };
+        Pos p1 = next_of(p0);
+        uint64_t y0 = load_y(p0), t0 = load_t(p0);
+        uint64_t y1 = load_y(p1.valid ? p1 : p0), t1 = load_t(p1.valid ? p1 : p0);
         for (;;) {
-            const Pos pb = advance(pa);
-            int64_t nqb = nqa;
-            uint32_t vb = va;
-            // the next loads are issued on every path (re-reading the current
-            // chunk when there is none) so the wait counts stay exact
-            issue(yb, pb.valid ? pb : pa);
-            if (pb.valid) {
-                if (pb.k != pa.k) {
-                    nqb = edge_of(pb.k);
-                    if (WEIGHTED) vb = (uint32_t)__builtin_amdgcn_readlane(vl, pb.k);
-                }
-            }
-            accumulate(ya, pa, nqa, va);
-            if (!pb.valid) break;
-            const Pos pn = advance(pb);
-            issue(ya, pn.valid ? pn : pb);
-            if (pn.valid) {
-                if (pn.k != pb.k) {
-                    nqa = edge_of(pn.k);
-                    if (WEIGHTED) va = (uint32_t)__builtin_amdgcn_readlane(vl, pn.k);
-                } else {
-                    nqa = nqb;
-                    va = vb;
-                }
-            }
-            accumulate(yb, pb, nqb, vb);
-            if (!pn.valid) break;
-            pa = pn;
+            const Pos p2 = next_of(p1);
+            const Pos l2 = p2.valid ? p2 : p0;
+            const uint64_t y2 = load_y(l2), t2 = load_t(l2);
+            accumulate(y0, t0, p0, val_of(p0));
+            if (!p1.valid) break;
+            const Pos p3 = next_of(p2);
+            const Pos l3 = p3.valid ? p3 : p1;
+            y0 = load_y(l3);
+            t0 = load_t(l3);
+            accumulate(y1, t1, p1, val_of(p1));
+            if (!p2.valid) break;
+            const Pos p4 = next_of(p3);
+            const Pos l4 = p4.valid ? p4 : p2;
+            y1 = load_y(l4);
+            t1 = load_t(l4);
+            accumulate(y2, t2, p2, val_of(p2));
+            if (!p3.valid) break;
+            p0 = p3;
+            p1 = p4;
         }
     }
     __syncthreads();
@@ -452,13 +464,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     if (bbase + x1 > A.nf) x1 = (int)(A.nf - bbase);
     const int s = s0 + j;
     const bool row_ok = s < A.ns;
+    const uint32_t *__restrict__ P = lds + j;
     float scale = 1.0f;
     if (WEIGHTED) scale = ldexpf(1.0f, -A.ws[(int64_t)slot * A.ws_stride].frac_bits);
     uint32_t acc = 0;
     if (x0 < x1)
-        for (int c = x0; c < x0 + kf - 1; ++c) acc += lds[c * kTileRows + j];
+        for (int c = x0; c < x0 + kf - 1; ++c) acc += P[c * kTileRows];
     for (int x = x0; x < x1; ++x) {
-        acc += lds[(x + kf - 1) * kTileRows + j];
+        acc += P[(x + kf - 1) * kTileRows];
         const int64_t b = bbase + x;
         if (MAP && row_ok) {
             if (WEIGHTED) A.map_f32[(int64_t)s * A.nf + b] = (float)acc * scale;
@@ -474,7 +487,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             }
             if (j == 0) atomicMax(A.colmax + (int64_t)slot * A.nf + b, key);
         }
-        acc -= lds[x * kTileRows + j];
+        acc -= P[x * kTileRows];
     }
 }
 
@@ -753,6 +766,13 @@ hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st) {
     const double S = ((double)kf * t_fft) * kTwo32;
     k_shifts<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, t, t0, S, fdot0, dfdot, g0, dg);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *dg, int64_t *rowsh,
+                             hipStream_t st) {
+    dim3 grid((ns_pad + 63) / 64, n_fft);
+    k_row_shifts<<<grid, 64, 0, st>>>(n_fft, ns_pad, dg, rowsh);
     return hipGetLastError();
 }
 
