@@ -68,28 +68,41 @@ def pct(xs, q):
     return xs[k]
 
 
-def cpu_baseline(w, rows_arg):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(w, rows_arg, target_s=20.0):
+    """The oracle as it stands, on a bounded sample of the same workload: the
+    full map and sub-band candidates of as many sky directions as fit in
+    about `target_s` seconds (a slice of the spin-down rows of one direction
+    if even one direction takes longer)."""
     import oracle
-    grid = w.grid
+    grid, sel = w.grid, w.sel
+    wts = None if w.weights is None else w.weights
+    n_sky_all = len(w.sky)
+
+    def one(k, rows):
+        wk = None if wts is None else (wts if wts.ndim == 1 else wts[k]).astype("float64")
+        m = oracle.hough_map(w.pm, grid, w.sky[k], weights=wk, rows=(0, rows))
+        if rows == grid.ns:
+            oracle.candidates(m, sel.width, sel.excl, sel.sep)
+
     rows = rows_arg or grid.ns
-    # size the sample to roughly 10-30 s of CPU work
     t0 = time.perf_counter()
-    oracle.hough_map(w.pm, grid, w.sky[0], weights=None if w.weights is None else w.weights.astype("float64"),
-                     rows=(0, min(grid.ns, 8)))
+    one(0, rows)
     probe = time.perf_counter() - t0
-    per_row = probe / min(grid.ns, 8)
-    if not rows_arg:
-        rows = int(max(8, min(grid.ns, 20.0 / max(per_row, 1e-6))))
+    if not rows_arg and probe > target_s:
+        rows = int(max(8, grid.ns * target_s / probe))
+    n = 1
+    if rows == grid.ns:
+        n = int(max(1, min(n_sky_all, round(target_s / max(probe, 1e-6)))))
     t0 = time.perf_counter()
-    oracle.hough_map(w.pm, grid, w.sky[0], weights=None if w.weights is None else w.weights.astype("float64"),
-                     rows=(0, rows))
+    for k in range(n):
+        one(k, rows)
     dt = time.perf_counter() - t0
-    updates = w.pm.n_peaks * rows
+    updates = w.pm.n_peaks * rows * n
+    what = ("%d sky directions, all %d spin-down rows, map + candidates" % (n, grid.ns) if rows == grid.ns
+            else "1 sky direction, spin-down rows 0..%d of %d, map only" % (rows - 1, grid.ns))
     return {"value": updates / dt, "unit": "cell-updates/s", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": "1 sky direction, spin-down rows 0..%d of %d, %d peaks (%.3g cell updates, %.1f s)"
-                      % (rows - 1, grid.ns, w.pm.n_peaks, updates, dt)}
+            "sample": "%s, %d peaks (%.3g cell updates, %.1f s)" % (what, w.pm.n_peaks, updates, dt)}
 
 
 SERVE_BANDS = [(8192.0, 40.0), (8192.0, 110.0), (4096.0, 180.0), (4096.0, 450.0),

@@ -6,23 +6,24 @@ definition as the C oracle but organised the other way round (cell-major
 instead of peak-major) and written independently in Python floats/ints, which
 are IEEE binary64 with round-half-even ``round`` and exact ``math.floor``.
 
-Definitions (Eqs. fdopp, uno, due, ncount, ncountadap, freqres, sdstep):
-  S = (K_f T_FFT) 2^32; G0_i = rint((fdot0 tau_i) S); dG_i = rint((dfdot tau_i) S)
+Definitions (Eqs. fdopp, uno, due, ncount, ncountadap, freqres, sdstep), with
+Q = 2^18 fixed-point steps per fine bin:
+  S = (K_f T_FFT) Q; G0_i = rint((fdot0 tau_i) S); dG_i = rint((dfdot tau_i) S)
   r_i = 1 / (1 + ((v_x n_x + v_y n_y) + v_z n_z))
-  X = floor((K_f k r_i) 2^32); L_s = X - b0 2^32 - K_f 2^31 - G0_i - s dG_i
-  cell (s, b) counts the peak iff L_s <= b 2^32 < L_s + K_f 2^32
+  X = floor((K_f k r_i) Q); L_s = X - b0 Q - K_f Q/2 - G0_i - s dG_i
+  cell (s, b) counts the peak iff L_s <= b Q < L_s + K_f Q
 """
 from __future__ import annotations
 
 import math
 
-TWO32 = 4294967296.0
-ONE32 = 1 << 32
+QD = 262144.0
+QI = 1 << 18
 
 
 def _fft_terms(t_i, t0, t_fft, kf, fdot0, dfdot):
     tau = t_i - t0
-    S = (float(kf) * t_fft) * TWO32
+    S = (float(kf) * t_fft) * QD
     return round((fdot0 * tau) * S), round((dfdot * tau) * S)
 
 
@@ -43,17 +44,17 @@ def hough_map_cells(pm, grid, nhat, weights=None):
         w = 1.0 if weights is None else float(weights[i])
         for p in range(int(pm.offsets[i]), int(pm.offsets[i + 1])):
             k = int(pm.bins[p])
-            X = math.floor((float(kf * k) * r) * TWO32)
+            X = math.floor((float(kf * k) * r) * QD)
             peaks.append((X, g0, dg, w))
     out = []
     for s in range(ns):
         row = []
         for b in range(nf):
-            lab = b * ONE32
+            lab = b * QI
             acc = 0.0
             for X, g0, dg, w in peaks:
-                L = X - b0 * ONE32 - kf * (ONE32 // 2) - g0 - s * dg
-                if L <= lab < L + kf * ONE32:
+                L = X - b0 * QI - kf * (QI // 2) - g0 - s * dg
+                if L <= lab < L + kf * QI:
                     acc += w
             row.append(acc)
         out.append(row)

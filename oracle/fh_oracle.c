@@ -17,14 +17,15 @@
  *   whose label lies in the stripe gains w_i (1 when unweighted)
  *                                                     (Eqs. ncount, ncountadap)
  *
- * The stripe edge is evaluated in an exactly specified Q32.32 fixed point so
- * that integer maps can be compared bit for bit:
- *   S      = (K_f * T_FFT) * 2^32
+ * The stripe edge is evaluated in an exactly specified fixed point with
+ * Q = 2^18 steps per fine bin, so that integer maps can be compared bit for
+ * bit:
+ *   S      = (K_f * T_FFT) * Q
  *   G0_i   = llrint((fdot0 * tau_i) * S),  dG_i = llrint((dfdot * tau_i) * S)
  *   D      = 1 + ((vx*nx + vy*ny) + vz*nz),  r = 1 / D
- *   X      = floor(((double)(K_f*k) * r) * 2^32)          (corrected centre)
- *   L_s    = X - b0*2^32 - K_f*2^31 - G0_i - s*dG_i       (left edge, row s)
- *   bin b is touched  iff  L_s <= b*2^32 < L_s + K_f*2^32
+ *   X      = floor(((double)(K_f*k) * r) * Q)             (corrected centre)
+ *   L_s    = X - b0*Q - K_f*Q/2 - G0_i - s*dG_i           (left edge, row s)
+ *   bin b is touched  iff  L_s <= b*Q < L_s + K_f*Q
  * All double operations are IEEE binary64, round to nearest even, evaluated in
  * the order written and never contracted into FMAs (build with
  * -ffp-contract=off).
@@ -37,22 +38,23 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define TWO32 4294967296.0
-#define ONE32 ((int64_t)1 << 32)
+/* fixed-point steps per fine bin */
+#define QD 262144.0
+#define QI ((int64_t)1 << 18)
 
-/* floor(a / 2^32) for any int64 a, written without relying on >> of negatives */
-static int64_t floor_div_2p32(int64_t a)
+/* floor(a / Q) for any int64 a, written without relying on >> of negatives */
+static int64_t floor_div_q(int64_t a)
 {
-    int64_t q = a / ONE32; /* truncates toward zero */
-    if (a % ONE32 != 0 && a < 0) q -= 1;
+    int64_t q = a / QI; /* truncates toward zero */
+    if (a % QI != 0 && a < 0) q -= 1;
     return q;
 }
 
-/* Per-FFT spin-down shifts in Q32.32 fine bins (Eqs. uno and sdstep). */
+/* Per-FFT spin-down shifts in fixed-point fine bins (Eqs. uno and sdstep). */
 void fho_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
                 double fdot0, double dfdot, int64_t *g0, int64_t *dg)
 {
-    double S = ((double)kf * t_fft) * TWO32;
+    double S = ((double)kf * t_fft) * QD;
     for (int32_t i = 0; i < n_fft; ++i) {
         double tau = t[i] - t0;
         g0[i] = llrint((fdot0 * tau) * S);
@@ -70,10 +72,10 @@ void fho_inv_doppler(int32_t n_fft, const double *v, const double *nhat, double 
     }
 }
 
-/* Corrected peak centre in Q32.32 fine bins. */
+/* Corrected peak centre in fixed-point fine bins. */
 int64_t fho_center(int32_t k, int32_t kf, double r)
 {
-    double x = ((double)((int64_t)kf * (int64_t)k) * r) * TWO32;
+    double x = ((double)((int64_t)kf * (int64_t)k) * r) * QD;
     return (int64_t)floor(x);
 }
 
@@ -102,12 +104,12 @@ int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
     }
     fho_shifts(n_fft, t, t0, t_fft, kf, fdot0, dfdot, g0, dg);
     fho_inv_doppler(n_fft, v, nhat, r);
-    /* stripe left edge at fdot = 0: E = X - b0*2^32 - K_f*2^31 */
+    /* stripe left edge at fdot = 0: E = X - b0*Q - K_f*Q/2 */
     for (int32_t i = 0; i < n_fft; ++i)
         for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p)
-            edge[p] = fho_center(bins[p], kf, r[i]) - b0 * ONE32 - (int64_t)kf * (ONE32 / 2);
+            edge[p] = fho_center(bins[p], kf, r[i]) - b0 * QI - (int64_t)kf * (QI / 2);
 
-    const int64_t width = (int64_t)kf * ONE32;
+    const int64_t width = (int64_t)kf * QI;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t s = row_lo; s < row_hi; ++s) {
         double *row = out + (int64_t)s * nf;
@@ -118,10 +120,10 @@ int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
             for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
                 int64_t L = edge[p] - shift;
                 /* candidate bins around the edge; membership decided by the test */
-                int64_t first = floor_div_2p32(L);
+                int64_t first = floor_div_q(L);
                 for (int64_t b = first; b <= first + kf; ++b) {
                     if (b < 0 || b >= nf) continue;
-                    int64_t lab = b * ONE32;
+                    int64_t lab = b * QI;
                     if (L <= lab && lab < L + width) row[b] += wi;
                 }
             }

@@ -49,8 +49,6 @@ struct TileArgs {
     const int64_t *Y;             // [slot][P] stripe edges (Q32.32, see prep kernel)
     const int2 *win;              // [slot][nrbg][nbb][N] peak windows
     const int64_t *dg;            // [N] row step of the stripe edge (Q32.32)
-    const int64_t *rowsh;         // [N][ns_pad] -s * dG_i
-    int32_t ns_pad;               // rows of all row blocks (nrb * 16)
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
     const WeightStats *ws;        // [slot * ws_stride] or nullptr
     int32_t ws_stride;            // 0: one shared weight vector, 1: one per slot
@@ -69,8 +67,6 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st);
-hipError_t launch_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *dg, int64_t *rowsh,
-                             hipStream_t st);
 hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
                                int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st);
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
@@ -97,6 +93,9 @@ hipError_t launch_pm_pack(int32_t n_fft, int32_t cap, const int32_t *scratch, co
 int tile_lds_bytes(int W, int kf);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).
 hipError_t init_kernel_attributes();
-int max_tile_bins(int kf);
+// widest tile (multiple of 64) that the LDS holds and that keeps 32-bit
+// tile-relative stripe edges exact when a row's spin-down step is at most
+// step_bins fine bins; 0 when no tile does
+int max_tile_bins(int kf, double step_bins);
 
 }  // namespace fh

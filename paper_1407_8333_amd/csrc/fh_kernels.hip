@@ -31,14 +31,25 @@ namespace fh {
 
 namespace {
 
-constexpr double kTwo32 = 4294967296.0;
-constexpr int64_t kOne32 = (int64_t)1 << 32;
+// Fixed point of stripe edges: kQ = 2^kFrac steps per fine bin.
+constexpr int kFrac = 18;
+constexpr double kQd = 262144.0;
+constexpr int64_t kQ = (int64_t)1 << kFrac;
 
-__device__ __forceinline__ int64_t shr32(int64_t a) { return a >> 32; }  // floor(a / 2^32)
+__device__ __forceinline__ int64_t shrq(int64_t a) { return a >> kFrac; }  // floor(a / kQ)
 
-// Stripe edge stored after each FFT's peaks (kYPad copies): far beyond every
-// tile, so a read past a window's end never adds inside a tile.
+// Stripe edge stored in the kYPad slots after each FFT's peaks (never inside
+// a window; the slots keep every FFT's run of edges followed by readable
+// memory).
 constexpr int64_t kYSentinel = (int64_t)1 << 61;
+
+// Tile-relative edges are 32-bit: with kFrac fractional bits a column must
+// stay inside +-2^(31 - kFrac) = +-8192.  A peak of a window starts within
+// 64 rows' worth of spin-down steps of the tile (the window covers a group of
+// 64 rows, the last row block may reach 16 rows past the grid), so
+// max_tile_bins bounds W + K_f + 80 (step + 1) + 64 below 8192.  kFarEdge
+// (6144 bins) then stays in range and beyond the dump column for every row.
+constexpr uint32_t kFarEdge = 6144u << kFrac;
 
 // ----------------------------------------------------------------------------
 // fills (graph-safe replacements for memset)
@@ -57,7 +68,7 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
 
 // ----------------------------------------------------------------------------
 // spin-down shifts: G0_i = rint((fdot0 tau_i) S), dG_i = rint((dfdot tau_i) S),
-// S = (K_f T_FFT) 2^32 (Eqs. uno, sdstep)
+// S = (K_f T_FFT) kQ (Eqs. uno, sdstep)
 
 __global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, double S,
                          double fdot0, double dfdot, int64_t *__restrict__ g0,
@@ -71,16 +82,6 @@ __global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, dou
     b = b * S;
     g0[i] = (int64_t)rint(a);
     dg[i] = (int64_t)rint(b);
-}
-
-// Row shifts of the stripe edge: T[i][s] = -s * dG_i, s < ns_pad (the rows
-// of every tile, including the padding rows of the last row block).
-__global__ void k_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *__restrict__ dg,
-                             int64_t *__restrict__ rowsh) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (s >= ns_pad || i >= n_fft) return;
-    rowsh[(int64_t)i * ns_pad + s] = -((int64_t)s * dg[i]);
 }
 
 // ----------------------------------------------------------------------------
@@ -134,11 +135,11 @@ __global__ void k_weight_stats(int32_t n, const float *__restrict__ w, int32_t w
 // ----------------------------------------------------------------------------
 // per-peak stripe edge.  For peak (i, k) and sky n:
 //   r = 1 / (1 + ((vx nx + vy ny) + vz nz))                     (Eq. fdopp)
-//   X = floor(((double)(K_f k) r) 2^32)
-//   Y = X - b0 2^32 - K_f 2^31 - G0_i + (2^32 - 1)
+//   X = floor(((double)(K_f k) r) kQ)
+//   Y = X - b0 kQ - K_f kQ/2 - G0_i + (kQ - 1)
 // so that the first fine bin of the stripe in row s is
-//   a_s = ceil((X - b0 2^32 - K_f 2^31 - G0_i - s dG_i) / 2^32)
-//       = floor((Y - s dG_i) / 2^32).
+//   a_s = ceil((X - b0 kQ - K_f kQ/2 - G0_i - s dG_i) / kQ)
+//       = floor((Y - s dG_i) / kQ).
 // One wave per FFT; grid.y = sky slot.
 
 __global__ void __launch_bounds__(256) k_prep(
@@ -158,14 +159,14 @@ __global__ void __launch_bounds__(256) k_prep(
     d = d + vi[2] * n[2];
     d = 1.0 + d;
     const double r = 1.0 / d;
-    const int64_t c = -b0 * kOne32 - (int64_t)kf * (kOne32 / 2) - g0[i] + (kOne32 - 1);
+    const int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
     // FFT i's edges start at offsets[i] + kYPad * i and are followed by kYPad
     // sentinels
     int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
     const int64_t e = offsets[i + 1];
     for (int64_t p = offsets[i] + lane; p < e; p += 64) {
         double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
-        x = x * kTwo32;
+        x = x * kQd;
         Ys[p] = (int64_t)floor(x) + c;
     }
     if (lane < kYPad) Ys[e + lane] = kYSentinel;
@@ -197,8 +198,8 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
     if (s_hi > ns - 1) s_hi = ns - 1;
     const int64_t c0 = (int64_t)jb * W - (kf - 1);
     const int64_t wc = (int64_t)W + kf - 1;
-    const int64_t q_lo = (int64_t)s_lo * dg[i] + c0 * kOne32;
-    const int64_t q_hi = (int64_t)s_hi * dg[i] + c0 * kOne32;
+    const int64_t q_lo = (int64_t)s_lo * dg[i] + c0 * kQ;
+    const int64_t q_hi = (int64_t)s_hi * dg[i] + c0 * kQ;
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int64_t p0 = offsets[i] + (int64_t)kYPad * i, p1 = offsets[i + 1] + (int64_t)kYPad * i;
     // lo: first peak whose larger column is >= 0
@@ -206,7 +207,7 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
     while (a < b) {
         int64_t m = (a + b) >> 1;
         int64_t y = Ys[m];
-        int64_t c1 = shr32(y - q_lo), c2 = shr32(y - q_hi);
+        int64_t c1 = shrq(y - q_lo), c2 = shrq(y - q_hi);
         int64_t cmax = c1 > c2 ? c1 : c2;
         if (cmax >= 0) b = m; else a = m + 1;
     }
@@ -216,7 +217,7 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
     while (a < b) {
         int64_t m = (a + b) >> 1;
         int64_t y = Ys[m];
-        int64_t c1 = shr32(y - q_lo), c2 = shr32(y - q_hi);
+        int64_t c1 = shrq(y - q_lo), c2 = shrq(y - q_hi);
         int64_t cmin = c1 < c2 ? c1 : c2;
         if (cmin >= wc) b = m; else a = m + 1;
     }
@@ -261,7 +262,7 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
             int jhi = nbb - 1, jlo = nbb;  // past the segment end
             if (p < p1) {
                 const int64_t y = Ys[p];
-                const int64_t a1 = shr32(y - q_lo), a2 = shr32(y - q_hi);
+                const int64_t a1 = shrq(y - q_lo), a2 = shrq(y - q_hi);
                 const int64_t amin = a1 < a2 ? a1 : a2, amax = a1 < a2 ? a2 : a1;
                 jhi = max(-1, min(nbb - 1, floor_div_w(amax + kf - 1, W, inv_w)));
                 jlo = max(0, min(nbb, floor_div_w(amin, W, inv_w)));
@@ -294,30 +295,31 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // column for updates that fall outside the tile.  The 16 lanes of a group
 // address 16 consecutive words, so an LDS atomic of a wave is bank-conflict
 // free whatever the stripe positions are.
-// Wave-uniform loads through the scalar unit: the address must be the same in
-// every lane, and the data must not change while the kernel runs.
-template <class T>
-__device__ __forceinline__ T ld_scalar(const T *p) {
-    return *(const __attribute__((address_space(4))) T *)p;
-}
-
-// One step of the accumulation: lane (group g, row j) adds the stripe of
-// peak 4u + g of the current block, whose edge sits in lane (g, u) and is
-// broadcast to the 16 lanes of the group with DPP row_newbcast:u.  The edge
-// is already relative to the tile's first column, so
-//   col = floor((Y' - s dG) / 2^32)  is the tile column of the stripe start,
-// and every column outside [0, W + K_f - 1) (negative ones wrap to large
-// unsigned values) goes to the dump column.
+// One step of the accumulation.  Lane (group g, row j) adds the stripe of
+// peak 4 (15 - U) + g of the current block: its edge, already made relative
+// to the tile (v = Y - c0 kQ - s0 dG, exact in 32 bits for every peak of a
+// window), sits in lane (g, U) and reaches the group's 16 lanes through DPP
+// row_newbcast:U fused into the add of the lane's row term t = -j dG.
+// col = floor((v + t) / kQ) is the tile column of the stripe start in row
+// s0 + j; columns outside [0, W + K_f - 1) (negative ones wrap to large
+// unsigned values) go to the dump column.
 template <int U>
-__device__ __forceinline__ void stripe_step(uint32_t ylo, uint32_t yhi, uint64_t t, uint32_t dump,
+__device__ __forceinline__ void stripe_step(uint32_t v, uint32_t t, uint32_t dump,
                                             uint32_t lane_off, uint32_t val,
                                             uint32_t *__restrict__ lds) {
-    const uint32_t blo = __builtin_amdgcn_update_dpp(0u, ylo, 0x150 + U, 0xF, 0xF, true);
-    const uint32_t bhi = __builtin_amdgcn_update_dpp(0u, yhi, 0x150 + U, 0xF, 0xF, true);
-    const uint64_t sum = (((uint64_t)bhi << 32) | blo) + t;
-    const uint32_t col = (uint32_t)(sum >> 32);
+    const uint32_t b = __builtin_amdgcn_update_dpp(0u, v, 0x150 + U, 0xF, 0xF, true);
+    const uint32_t col = (uint32_t)((int32_t)(b + t) >> kFrac);
     const uint32_t cu = col < dump ? col : dump;
     atomicAdd(lds + cu * kTileRows + lane_off, val);
+}
+
+// Steps U .. 15 in sequence.
+template <int U>
+__device__ __forceinline__ void stripe_steps(uint32_t v, uint32_t t, uint32_t dump,
+                                             uint32_t lane_off, uint32_t val,
+                                             uint32_t *__restrict__ lds) {
+    stripe_step<U>(v, t, dump, lane_off, val, lds);
+    if constexpr (U < 15) stripe_steps<U + 1>(v, t, dump, lane_off, val, lds);
 }
 
 // Peaks of one FFT handled per block (4 lane groups x 16 steps).
@@ -350,105 +352,87 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const int32_t c0 = jb * W - (kf - 1);
     const int g = rb / kRowBlocksPerGroup;
     const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * A.n_fft;
-    const int64_t *__restrict__ Ys = A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft);
+    // low 32 bits of the stripe edges (all the tile needs: see stripe_step)
+    const uint32_t *__restrict__ Ylo =
+        reinterpret_cast<const uint32_t *>(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
     const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
     const uint32_t dump = (uint32_t)wc;
     const uint32_t lane_off = (uint32_t)j;
-    const int lane_peak = 4 * j + grp;  // this lane's peak within a block
-    const int64_t *__restrict__ rowsh = A.rowsh + (s0 + j);
+    // lane (g, j) holds peak 4 (15 - j) + g of a block
+    const int lane_peak = 4 * (15 - j) + grp;
+    const uint32_t lane_word = 2u * (uint32_t)lane_peak;  // low word of its edge
+    const int neg_j = -j;
+    const uint32_t c0q = (uint32_t)c0 << kFrac;
 
     // Each wave takes a contiguous run of FFTs, read 64 at a time (one per
-    // lane).  A block of up to 64 peaks of one FFT is loaded with one wave
-    // load (one edge per lane) together with the FFT's row shifts, while the
-    // previous block is accumulated.
+    // lane).  A block of up to 64 peaks of one FFT arrives with one wave load
+    // (one edge per lane), issued while the previous block is accumulated.
     const int per = (A.n_fft + nwave - 1) / nwave;
     const int i_begin = wave * per;
     const int i_end = min(A.n_fft, i_begin + per);
 
-    struct Pos {
-        int k, p0, hi;
-        bool valid;
-    };
     for (int ib = i_begin; ib < i_end; ib += 64) {
         const int myi = ib + lane;
         int2 wl = make_int2(0, 0);
+        int32_t dl = 0;
         uint32_t vl = 1u;
         if (myi < i_end) {
             wl = win[myi];
+            dl = (int32_t)A.dg[myi];
             if (WEIGHTED) vl = wq[myi];
         }
-        const uint64_t mask = __ballot(wl.x < wl.y);
+        uint64_t mask = __ballot(wl.x < wl.y);
         if (mask == 0) continue;
-        auto advance = [&](const Pos &c) {
-            Pos n = c;
-            n.p0 = c.p0 + kBlock;
-            if (n.p0 >= c.hi) {
-                const uint64_t rest = c.k >= 63 ? 0ull : mask & (~0ull << (c.k + 1));
-                if (rest == 0) {
-                    n.valid = false;
+        // current block: FFT k, peaks [p0, hi)
+        int k = __builtin_ctzll(mask);
+        int p0 = __builtin_amdgcn_readlane(wl.x, k);
+        int hi = __builtin_amdgcn_readlane(wl.y, k);
+        uint32_t ycur = (Ylo + 2 * (int64_t)p0)[lane_word];
+        for (;;) {
+            // per-FFT terms (scalar dG; the lane's row term t = -j dG)
+            const int32_t dG = __builtin_amdgcn_readlane(dl, k);
+            const uint32_t base =
+                __builtin_amdgcn_readfirstlane(c0q + (uint32_t)s0 * (uint32_t)dG);
+            const uint32_t t = (uint32_t)(neg_j * dG);
+            uint32_t val = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, k) : 1u;
+            asm volatile("" : "+v"(val));
+            // next block (same FFT, or the next non-empty one of the batch)
+            int nk = k, np0 = p0 + kBlock, nhi = hi;
+            bool more = true;
+            if (np0 >= hi) {
+                mask &= mask - 1;  // clear bit k (the lowest set bit)
+                if (mask == 0) {
+                    more = false;
+                    np0 = p0;
                 } else {
-                    n.k = __builtin_ctzll(rest);
-                    n.p0 = __builtin_amdgcn_readlane(wl.x, n.k);
-                    n.hi = __builtin_amdgcn_readlane(wl.y, n.k);
+                    nk = __builtin_ctzll(mask);
+                    np0 = __builtin_amdgcn_readlane(wl.x, nk);
+                    nhi = __builtin_amdgcn_readlane(wl.y, nk);
                 }
             }
-            return n;
-        };
-        // stripe edge relative to the tile's first column c0
-        auto load_y = [&](const Pos &c) { return (uint64_t)Ys[c.p0 + lane_peak] - ((uint64_t)(uint32_t)c0 << 32); };
-        auto load_t = [&](const Pos &c) { return (uint64_t)rowsh[(int64_t)(ib + c.k) * A.ns_pad]; };
-        auto accumulate = [&](uint64_t y, uint64_t t, const Pos &c, uint32_t val) {
-            const int cnt = c.hi - c.p0;
-            const uint32_t ylo = (uint32_t)y, yhi = (uint32_t)(y >> 32);
-#define FH_STEP(U)                                                                   \
-    if ((U) == 0 || 4 * (U) < cnt) stripe_step<U>(ylo, yhi, t, dump, lane_off, val, lds);
-            FH_STEP(0) FH_STEP(1) FH_STEP(2) FH_STEP(3) FH_STEP(4) FH_STEP(5) FH_STEP(6) FH_STEP(7)
-            FH_STEP(8) FH_STEP(9) FH_STEP(10) FH_STEP(11) FH_STEP(12) FH_STEP(13) FH_STEP(14) FH_STEP(15)
-#undef FH_STEP
-        };
-
-        // Three blocks in flight: the loop body is unrolled over the three
-        // register slots, and every slot issues its loads on every path
-        // (re-reading the last valid block once the stream has ended) so the
-        // hardware wait counts stay exact.
-        Pos p0;
-        p0.k = __builtin_ctzll(mask);
-        p0.p0 = __builtin_amdgcn_readlane(wl.x, p0.k);
-        p0.hi = __builtin_amdgcn_readlane(wl.y, p0.k);
-        p0.valid = true;
-        auto next_of = [&](const Pos &c) {
-            Pos n = advance(c);
-            if (!c.valid) n.valid = false;
-            return n;
-        };
-        auto val_of = [&](const Pos &c) {
-            uint32_t v = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, c.k) : 1u;
-            asm volatile("" : "+v"(v));
-            return v;
-        };
-        Pos p1 = next_of(p0);
-        uint64_t y0 = load_y(p0), t0 = load_t(p0);
-        uint64_t y1 = load_y(p1.valid ? p1 : p0), t1 = load_t(p1.valid ? p1 : p0);
-        for (;;) {
-            const Pos p2 = next_of(p1);
-            const Pos l2 = p2.valid ? p2 : p0;
-            const uint64_t y2 = load_y(l2), t2 = load_t(l2);
-            accumulate(y0, t0, p0, val_of(p0));
-            if (!p1.valid) break;
-            const Pos p3 = next_of(p2);
-            const Pos l3 = p3.valid ? p3 : p1;
-            y0 = load_y(l3);
-            t0 = load_t(l3);
-            accumulate(y1, t1, p1, val_of(p1));
-            if (!p2.valid) break;
-            const Pos p4 = next_of(p3);
-            const Pos l4 = p4.valid ? p4 : p2;
-            y1 = load_y(l4);
-            t1 = load_t(l4);
-            accumulate(y2, t2, p2, val_of(p2));
-            if (!p3.valid) break;
-            p0 = p3;
-            p1 = p4;
+            // issued on every path (re-reading this block at the end) so the
+            // wait counts stay exact
+            const uint32_t ynext = (Ylo + 2 * (int64_t)np0)[lane_word];
+            // lanes past the block's last peak get an edge far right of the
+            // tile (every row's column lands in the dump)
+            const uint32_t v = lane_peak < hi - p0 ? ycur - base : kFarEdge;
+            const int n = min(16, (hi - p0 + 3) >> 2);
+            // steps 16 - n .. 15 (the block's first 4 n peaks), one straight
+            // run per case
+            switch (n) {
+#define FH_CASE(N) \
+    case N: stripe_steps<16 - N>(v, t, dump, lane_off, val, lds); break;
+                FH_CASE(1) FH_CASE(2) FH_CASE(3) FH_CASE(4) FH_CASE(5) FH_CASE(6) FH_CASE(7)
+                FH_CASE(8) FH_CASE(9) FH_CASE(10) FH_CASE(11) FH_CASE(12) FH_CASE(13) FH_CASE(14)
+                FH_CASE(15) FH_CASE(16)
+#undef FH_CASE
+                default: break;
+            }
+            if (!more) break;
+            k = nk;
+            p0 = np0;
+            hi = nhi;
+            ycur = ynext;
         }
     }
     __syncthreads();
@@ -744,9 +728,13 @@ inline unsigned grid_for(int64_t n, int block) {
 
 int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + 1) * 4; }
 
-int max_tile_bins(int kf) {
+int max_tile_bins(int kf, double step_bins) {
     const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dump
     int w = words - kf;                                           // W + kf - 1 + 1 <= words
+    // 32-bit tile-relative edges (see kFarEdge)
+    const double m = ceil(step_bins) + 1.0;
+    const double wr = (double)(1 << (31 - kFrac)) - 64.0 - kf - 80.0 * m;
+    if (wr < (double)w) w = wr < 0.0 ? 0 : (int)wr;
     return (w / 64) * 64;
 }
 
@@ -764,15 +752,8 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
 
 hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st) {
-    const double S = ((double)kf * t_fft) * kTwo32;
+    const double S = ((double)kf * t_fft) * kQd;
     k_shifts<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, t, t0, S, fdot0, dfdot, g0, dg);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_shifts(int32_t n_fft, int32_t ns_pad, const int64_t *dg, int64_t *rowsh,
-                             hipStream_t st) {
-    dim3 grid((ns_pad + 63) / 64, n_fft);
-    k_row_shifts<<<grid, 64, 0, st>>>(n_fft, ns_pad, dg, rowsh);
     return hipGetLastError();
 }
 

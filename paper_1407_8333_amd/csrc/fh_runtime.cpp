@@ -117,18 +117,18 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, rowsh, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
+    DevBuf g0, dg, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
     PinnedBuf h_sky, h_order;
     // tile order of the persistent schedule currently held in `order`
     int64_t order_slots = -1, order_nrb = -1, order_nbb = -1;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &rowsh, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (const DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &rowsh, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
             b->release();
         h_sky.release();
         h_order.release();
@@ -186,6 +186,17 @@ fh_status check_ctx(fh_ctx *ctx) {
     return FH_OK;
 }
 
+// Largest spin-down step of one row, in fine bins: |dfdot tau| K_f T_FFT
+// (Eq. sdstep) over the FFTs' reference-time offsets tau, plus rounding.
+double row_step_bins(const fh_peakmap *pm, const fh_grid *g) {
+    const double tau = std::max(std::fabs(pm->t_min - g->t0), std::fabs(pm->t_max - g->t0));
+    return std::fabs(g->dfdot) * tau * ((double)g->kf * pm->t_fft) + 1e-6;
+}
+
+int tile_bins_limit(const fh_peakmap *pm, const fh_grid *g) {
+    return max_tile_bins(g->kf, row_step_bins(pm, g));
+}
+
 fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
     if (!g) return fail(FH_E_INVALID, "grid is NULL");
@@ -202,6 +213,9 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     const double S = (double)g->kf * pm->t_fft;
     const double gmax = (std::fabs(g->fdot0) + std::fabs(g->dfdot) * g->ns) * tau * S;
     if (!(gmax < 1e12)) return fail(FH_E_INVALID, "spin-down shifts exceed the fixed-point range");
+    if (max_tile_bins(g->kf, row_step_bins(pm, g)) < 64)
+        return fail(FH_E_UNSUPPORTED, "spin-down step of %.6g fine bins per row is too large for a tile",
+                    row_step_bins(pm, g));
     return FH_OK;
 }
 
@@ -220,7 +234,7 @@ std::tuple<int, int, int, int, int> tune_key(const fh_peakmap *pm, const fh_grid
 
 int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested,
                      bool weighted = false) {
-    const int wmax = max_tile_bins(g->kf);
+    const int wmax = tile_bins_limit(pm, g);
     if (requested > 0) return std::min(((requested + 63) / 64) * 64, wmax);
     auto it = ctx->tuned.find(tune_key(pm, g, weighted));
     if (it != ctx->tuned.end()) return it->second;
@@ -265,7 +279,7 @@ struct Timed {
 };
 
 struct ChunkBufs {
-    int64_t *g0, *dg, *rowsh, *Y;
+    int64_t *g0, *dg, *Y;
     int2 *win;
     unsigned long long *colmax;
     uint32_t *wq;
@@ -280,7 +294,6 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     fh_status s;
     if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
-    if ((s = ctx->cur->rowsh.ensure((size_t)8 * N * p.nrb * kTileRows, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
@@ -294,7 +307,6 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->err.ensure(4, st))) return s;
     b.g0 = (int64_t *)ctx->cur->g0.ptr;
     b.dg = (int64_t *)ctx->cur->dg.ptr;
-    b.rowsh = (int64_t *)ctx->cur->rowsh.ptr;
     b.Y = (int64_t *)ctx->cur->Y.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
     b.colmax = (unsigned long long *)ctx->cur->colmax.ptr;
@@ -324,8 +336,6 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.Y = b.Y;
     a.win = b.win;
     a.dg = b.dg;
-    a.rowsh = b.rowsh;
-    a.ns_pad = p.nrb * kTileRows;
     a.wq = weighted ? b.wq : nullptr;
     a.ws = weighted ? b.ws : nullptr;
     a.ws_stride = ws_stride;
@@ -354,7 +364,6 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                         const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
     HIP_OK(launch_shifts(pm->n_fft, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.g0, b.dg, st));
-    HIP_OK(launch_row_shifts(pm->n_fft, p.nrb * kTileRows, b.dg, b.rowsh, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
@@ -473,7 +482,7 @@ fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const 
 fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sky,
                    const double *sky, const float *d_w, int w_stride, hipStream_t st) {
     const bool weighted = d_w != nullptr;
-    const int wmax = max_tile_bins(g->kf);
+    const int wmax = tile_bins_limit(pm, g);
     const int wcap = std::min(wmax, std::max(64, ((g->nf + 63) / 64) * 64));
     std::vector<int> cands;
     for (int w : {512, 832, 1280, 1792, 2176})
@@ -850,7 +859,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky, (uint64_t)(uintptr_t)b.order,
-        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowsh};
+        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg};
     fh_ctx::GraphEntry *ge = nullptr;
     for (auto &e : ctx->graphs)
         if (e.key == key) ge = &e;
