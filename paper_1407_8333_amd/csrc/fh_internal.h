@@ -20,10 +20,11 @@ constexpr int kTileThreads = 1024;
 constexpr int kLdsBytes = 163840;
 // Bytes of LDS reserved for the scheduler slot and alignment.
 constexpr int kLdsReserve = 256;
+// dump columns after a tile's W + K_f - 1 columns (one per lane group)
+constexpr int kDumpCols = 4;
 // Number of XCDs of an MI355X; workgroup w is dispatched to XCD w % 8.
 constexpr int kXcds = 8;
-// Sentinel stripe edges appended after each FFT's peaks: a block read may
-// run up to 3 peaks past a window's end into accumulated steps.
+// Padding entries after each FFT's stripe edges (never inside a window).
 constexpr int kYPad = 16;
 // Stripe edges per sky direction: every peak plus kYPad per FFT, plus one
 // block of slack at the end (a block load reads up to 63 past a window start).
@@ -46,9 +47,10 @@ struct TileArgs {
     int32_t kf, nf, ns, W;        // W: fine bins per tile
     int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
     int32_t n_slots;              // sky directions in this chunk
-    const int64_t *Y;             // [slot][P] stripe edges (Q32.32, see prep kernel)
+    const int64_t *Y;             // [slot][P] stripe edges (2^-18 fine bins, see prep kernel)
     const int2 *win;              // [slot][nrbg][nbb][N] peak windows
-    const int64_t *dg;            // [N] row step of the stripe edge (Q32.32)
+    const int64_t *dg;            // [N] row step of the stripe edge (2^-18 fine bins)
+    const int32_t *rowt;          // [N][16] row terms -j dG_i mod 2^32, j < 16
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
     const WeightStats *ws;        // [slot * ws_stride] or nullptr
     int32_t ws_stride;            // 0: one shared weight vector, 1: one per slot
@@ -67,6 +69,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st);
+hipError_t launch_row_terms(int32_t n_fft, const int64_t *dg, int32_t *rowt, hipStream_t st);
 hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
                                int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st);
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,

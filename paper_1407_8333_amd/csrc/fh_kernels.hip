@@ -84,6 +84,16 @@ __global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, dou
     dg[i] = (int64_t)rint(b);
 }
 
+// Row terms of a tile: T[i][j] = -j dG_i (mod 2^32), the offset of row s0 + j
+// from row s0 of every tile.
+__global__ void k_row_terms(int32_t n_fft, const int64_t *__restrict__ dg,
+                            int32_t *__restrict__ rowt) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x >= (int64_t)n_fft * kTileRows) return;
+    const int64_t i = x / kTileRows, j = x % kTileRows;
+    rowt[x] = (int32_t)(uint32_t)(uint64_t)(-j * dg[i]);
+}
+
 // ----------------------------------------------------------------------------
 // weight statistics and fixed-point scale (Eq. ncountadap)
 
@@ -295,14 +305,14 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // column for updates that fall outside the tile.  The 16 lanes of a group
 // address 16 consecutive words, so an LDS atomic of a wave is bank-conflict
 // free whatever the stripe positions are.
-// One step of the accumulation.  Lane (group g, row j) adds the stripe of
-// peak 4 (15 - U) + g of the current block: its edge, already made relative
-// to the tile (v = Y - c0 kQ - s0 dG, exact in 32 bits for every peak of a
-// window), sits in lane (g, U) and reaches the group's 16 lanes through DPP
-// row_newbcast:U fused into the add of the lane's row term t = -j dG.
-// col = floor((v + t) / kQ) is the tile column of the stripe start in row
-// s0 + j; columns outside [0, W + K_f - 1) (negative ones wrap to large
-// unsigned values) go to the dump column.
+// One step of the accumulation.  Lane (group g, row j) adds the stripe of the
+// peak held by lane (g, U): its edge, already made relative to the tile
+// (v = Y - c0 kQ - s0 dG, exact in 32 bits for every peak of a window),
+// reaches the group's 16 lanes through DPP row_newbcast:U fused into the add
+// of the lane's row term t = -j dG.  col = floor((v + t) / kQ) is the tile
+// column of the stripe start in row s0 + j; columns outside
+// [0, W + K_f - 1) (negative ones wrap to large unsigned values) go to the
+// group's dump column.
 template <int U>
 __device__ __forceinline__ void stripe_step(uint32_t v, uint32_t t, uint32_t dump,
                                             uint32_t lane_off, uint32_t val,
@@ -313,17 +323,48 @@ __device__ __forceinline__ void stripe_step(uint32_t v, uint32_t t, uint32_t dum
     atomicAdd(lds + cu * kTileRows + lane_off, val);
 }
 
-// Steps U .. 15 in sequence.
-template <int U>
-__device__ __forceinline__ void stripe_steps(uint32_t v, uint32_t t, uint32_t dump,
-                                             uint32_t lane_off, uint32_t val,
-                                             uint32_t *__restrict__ lds) {
+template <int U, int E>
+__device__ __forceinline__ void stripe_run(uint32_t v, uint32_t t, uint32_t dump,
+                                           uint32_t lane_off, uint32_t val,
+                                           uint32_t *__restrict__ lds) {
     stripe_step<U>(v, t, dump, lane_off, val, lds);
-    if constexpr (U < 15) stripe_steps<U + 1>(v, t, dump, lane_off, val, lds);
+    if constexpr (U + 1 < E) stripe_run<U + 1, E>(v, t, dump, lane_off, val, lds);
 }
 
-// Peaks of one FFT handled per block (4 lane groups x 16 steps).
-constexpr int kBlock = 64;
+// A chunk of up to 64 peaks of one FFT occupies the lanes named by a 16-bit
+// pattern m(n), n = ceil(peaks / 4), built from fixed runs so that each run
+// is one straight sequence of steps: lanes 0-7 (n & 8), 8-11 (n & 4),
+// 12-13 (n & 2), 14 (n & 1); n = 16 uses all 16.  Lane j of every group
+// holds peak 4 q + g, q = the number of pattern lanes below j.
+__device__ __forceinline__ uint32_t chunk_pattern(int n) {
+    if (n >= 16) return 0xFFFFu;
+    return ((1u << (n & 8)) - 1u) | (((1u << (n & 4)) - 1u) << 8) |
+           (((1u << (n & 2)) - 1u) << 12) | (((1u << (n & 1)) - 1u) << 14);
+}
+
+__device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t, uint32_t dump,
+                                             uint32_t lane_off, uint32_t val,
+                                             uint32_t *__restrict__ lds) {
+    if (m & 0x00FFu) stripe_run<0, 8>(v, t, dump, lane_off, val, lds);
+    if (m & 0x0F00u) stripe_run<8, 12>(v, t, dump, lane_off, val, lds);
+    if (m & 0x3000u) stripe_run<12, 14>(v, t, dump, lane_off, val, lds);
+    if (m & 0x4000u) stripe_run<14, 15>(v, t, dump, lane_off, val, lds);
+    if (m & 0x8000u) stripe_run<15, 16>(v, t, dump, lane_off, val, lds);
+}
+
+// One block: four FFTs of a wave's run, FFT 4 b + g in lane group g.  Lane
+// (g, j) holds its group's window, row term -j dG and weight, and the stripe
+// edges of its peaks in up to two chunks of 16.
+struct Quad {
+    int lo, hi;          // peak window [lo, hi) of the group's FFT
+    int32_t dg;          // row step dG of the group's FFT
+    uint32_t t, wq;      // row term -j dG (mod 2^32); fixed-point weight
+    int cnt;             // peaks in the window (0 past the wave's run)
+    int32_t q1, q2;      // chunk positions of the lane's peaks
+    uint32_t y0, y1;     // low words of their stripe edges
+    uint32_t m1, m2;     // lane patterns of the two chunks
+    int cmax;            // largest window of the four groups
+};
 
 template <bool WEIGHTED, bool MAP, bool COLMAX>
 __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, int jb,
@@ -336,8 +377,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const int grp = lane >> 4;
     const int W = A.W, kf = A.kf;
     const int wc = W + kf - 1;
-    // LDS column c holds fine bin c0 + c, c in [0, wc); column wc is the dump.
-    const int nwords = kTileRows * (wc + 1);
+    // LDS column c holds fine bin c0 + c, c in [0, wc); columns wc + g are
+    // the dumps of the four lane groups.
+    const int nwords = kTileRows * (wc + kDumpCols);
 
     for (int x = tid * 4; x < nwords; x += blockDim.x * 4) {
         if (x + 3 < nwords) {
@@ -355,84 +397,91 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     // low 32 bits of the stripe edges (all the tile needs: see stripe_step)
     const uint32_t *__restrict__ Ylo =
         reinterpret_cast<const uint32_t *>(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
+    // low words of the row steps (they fit in 32 bits: see max_tile_bins)
+    const int32_t *__restrict__ dg32 = reinterpret_cast<const int32_t *>(A.dg);
     const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
-    const uint32_t dump = (uint32_t)wc;
+    const uint32_t dump = (uint32_t)(wc + grp);
     const uint32_t lane_off = (uint32_t)j;
-    // lane (g, j) holds peak 4 (15 - j) + g of a block
-    const int lane_peak = 4 * (15 - j) + grp;
-    const uint32_t lane_word = 2u * (uint32_t)lane_peak;  // low word of its edge
-    const int neg_j = -j;
     const uint32_t c0q = (uint32_t)c0 << kFrac;
+    const uint32_t below = (1u << j) - 1u;           // pattern lanes below j
+    const uint32_t mtab = chunk_pattern(lane);       // lane n holds m(n), n <= 16
 
-    // Each wave takes a contiguous run of FFTs, read 64 at a time (one per
-    // lane).  A block of up to 64 peaks of one FFT arrives with one wave load
-    // (one edge per lane), issued while the previous block is accumulated.
-    const int per = (A.n_fft + nwave - 1) / nwave;
-    const int i_begin = wave * per;
+    // Each wave takes a contiguous run of FFTs, four at a time (one per lane
+    // group).  A block's window data are loaded two blocks ahead and its
+    // stripe edges one block ahead (a ring of three blocks), so that the
+    // accumulation of a block never waits for memory.  Every load is issued
+    // on every path (clamped to the wave's last FFT) so that the wait counts
+    // stay exact.
+    int per = (A.n_fft + nwave - 1) / nwave;
+    per = (per + 3) & ~3;
+    const int i_begin = min(A.n_fft, wave * per);
     const int i_end = min(A.n_fft, i_begin + per);
+    const int nblk = (i_end - i_begin + 3) >> 2;
 
-    for (int ib = i_begin; ib < i_end; ib += 64) {
-        const int myi = ib + lane;
-        int2 wl = make_int2(0, 0);
-        int32_t dl = 0;
-        uint32_t vl = 1u;
-        if (myi < i_end) {
-            wl = win[myi];
-            dl = (int32_t)A.dg[myi];
-            if (WEIGHTED) vl = wq[myi];
+    // window data of block bb (stage 1)
+    auto stage_w = [&](Quad &Q, int bb) {
+        const int f = i_begin + 4 * bb + grp;
+        const int fc = min(f, i_end - 1);
+        const int2 w2 = win[fc];
+        Q.lo = w2.x;
+        Q.hi = f < i_end ? w2.y : w2.x;
+        Q.t = (uint32_t)A.rowt[(int64_t)fc * kTileRows + j];
+        Q.dg = dg32[2 * (int64_t)fc];
+        Q.wq = WEIGHTED ? wq[fc] : 1u;
+    };
+    // stripe edges of block bb (stage 2): the chunk sizes follow the largest
+    // window of the four groups
+    auto stage_y = [&](Quad &Q) {
+        Q.cnt = Q.hi - Q.lo;
+        const int c0_ = __builtin_amdgcn_readlane(Q.cnt, 0);
+        const int c1_ = __builtin_amdgcn_readlane(Q.cnt, 16);
+        const int c2_ = __builtin_amdgcn_readlane(Q.cnt, 32);
+        const int c3_ = __builtin_amdgcn_readlane(Q.cnt, 48);
+        Q.cmax = max(max(c0_, c1_), max(c2_, c3_));
+        const int n1 = min(Q.cmax, 16);
+        const int n2 = min(max(Q.cmax - 16, 0), 16);
+        Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
+        Q.m2 = __builtin_amdgcn_readlane(mtab, n2);
+        Q.q1 = (int32_t)__builtin_popcount(Q.m1 & below);
+        Q.q2 = 16 + (int32_t)__builtin_popcount(Q.m2 & below);
+        Q.y0 = Ylo[2 * (int64_t)(Q.lo + Q.q1)];
+        Q.y1 = Ylo[2 * (int64_t)(Q.lo + Q.q2)];
+    };
+    auto consume = [&](const Quad &Q) {
+        const uint32_t base = c0q + (uint32_t)s0 * (uint32_t)Q.dg;
+        uint32_t val = Q.wq;
+        asm volatile("" : "+v"(val));
+        const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
+        stripe_chunk(Q.m1, v0, Q.t, dump, lane_off, val, lds);
+        if (Q.cmax > 16) {
+            const uint32_t v1 = Q.q2 < Q.cnt ? Q.y1 - base : kFarEdge;
+            stripe_chunk(Q.m2, v1, Q.t, dump, lane_off, val, lds);
         }
-        uint64_t mask = __ballot(wl.x < wl.y);
-        if (mask == 0) continue;
-        // current block: FFT k, peaks [p0, hi)
-        int k = __builtin_ctzll(mask);
-        int p0 = __builtin_amdgcn_readlane(wl.x, k);
-        int hi = __builtin_amdgcn_readlane(wl.y, k);
-        uint32_t ycur = (Ylo + 2 * (int64_t)p0)[lane_word];
-        for (;;) {
-            // per-FFT terms (scalar dG; the lane's row term t = -j dG)
-            const int32_t dG = __builtin_amdgcn_readlane(dl, k);
-            const uint32_t base =
-                __builtin_amdgcn_readfirstlane(c0q + (uint32_t)s0 * (uint32_t)dG);
-            const uint32_t t = (uint32_t)(neg_j * dG);
-            uint32_t val = WEIGHTED ? (uint32_t)__builtin_amdgcn_readlane(vl, k) : 1u;
-            asm volatile("" : "+v"(val));
-            // next block (same FFT, or the next non-empty one of the batch)
-            int nk = k, np0 = p0 + kBlock, nhi = hi;
-            bool more = true;
-            if (np0 >= hi) {
-                mask &= mask - 1;  // clear bit k (the lowest set bit)
-                if (mask == 0) {
-                    more = false;
-                    np0 = p0;
-                } else {
-                    nk = __builtin_ctzll(mask);
-                    np0 = __builtin_amdgcn_readlane(wl.x, nk);
-                    nhi = __builtin_amdgcn_readlane(wl.y, nk);
-                }
-            }
-            // issued on every path (re-reading this block at the end) so the
-            // wait counts stay exact
-            const uint32_t ynext = (Ylo + 2 * (int64_t)np0)[lane_word];
-            // lanes past the block's last peak get an edge far right of the
-            // tile (every row's column lands in the dump)
-            const uint32_t v = lane_peak < hi - p0 ? ycur - base : kFarEdge;
-            const int n = min(16, (hi - p0 + 3) >> 2);
-            // steps 16 - n .. 15 (the block's first 4 n peaks), one straight
-            // run per case
-            switch (n) {
-#define FH_CASE(N) \
-    case N: stripe_steps<16 - N>(v, t, dump, lane_off, val, lds); break;
-                FH_CASE(1) FH_CASE(2) FH_CASE(3) FH_CASE(4) FH_CASE(5) FH_CASE(6) FH_CASE(7)
-                FH_CASE(8) FH_CASE(9) FH_CASE(10) FH_CASE(11) FH_CASE(12) FH_CASE(13) FH_CASE(14)
-                FH_CASE(15) FH_CASE(16)
-#undef FH_CASE
-                default: break;
-            }
-            if (!more) break;
-            k = nk;
-            p0 = np0;
-            hi = nhi;
-            ycur = ynext;
+        // windows longer than 32 peaks: further chunks, loaded here
+        for (int off = 32; off < Q.cmax; off += 16) {
+            const uint32_t m = __builtin_amdgcn_readlane(mtab, min(Q.cmax - off, 16));
+            const int32_t q = off + (int32_t)__builtin_popcount(m & below);
+            uint32_t v = kFarEdge;
+            if (q < Q.cnt) v = Ylo[2 * (int64_t)(Q.lo + q)] - base;
+            stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
+        }
+    };
+
+    if (nblk > 0) {
+        Quad qa, qb, qc;
+        stage_w(qa, 0);
+        stage_w(qb, 1);
+        stage_y(qa);
+        for (int b = 0; b < nblk; b += 3) {
+            stage_w(qc, b + 2);
+            stage_y(qb);
+            consume(qa);
+            stage_w(qa, b + 3);
+            stage_y(qc);
+            consume(qb);
+            stage_w(qb, b + 4);
+            stage_y(qa);
+            consume(qc);
         }
     }
     __syncthreads();
@@ -726,11 +775,11 @@ inline unsigned grid_for(int64_t n, int block) {
 
 }  // namespace
 
-int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + 1) * 4; }
+int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + kDumpCols) * 4; }
 
 int max_tile_bins(int kf, double step_bins) {
-    const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dump
-    int w = words - kf;                                           // W + kf - 1 + 1 <= words
+    const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dumps
+    int w = words - kf + 1 - kDumpCols;                           // W + kf - 1 + dumps <= words
     // 32-bit tile-relative edges (see kFarEdge)
     const double m = ceil(step_bins) + 1.0;
     const double wr = (double)(1 << (31 - kFrac)) - 64.0 - kf - 80.0 * m;
@@ -754,6 +803,13 @@ hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft
                          double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st) {
     const double S = ((double)kf * t_fft) * kQd;
     k_shifts<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, t, t0, S, fdot0, dfdot, g0, dg);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_terms(int32_t n_fft, const int64_t *dg, int32_t *rowt, hipStream_t st) {
+    const int64_t n = (int64_t)n_fft * kTileRows;
+    if (n <= 0) return hipSuccess;
+    k_row_terms<<<grid_for(n, 256), 256, 0, st>>>(n_fft, dg, rowt);
     return hipGetLastError();
 }
 

@@ -117,18 +117,18 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
+    DevBuf g0, dg, rowt, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
     PinnedBuf h_sky, h_order;
     // tile order of the persistent schedule currently held in `order`
     int64_t order_slots = -1, order_nrb = -1, order_nbb = -1;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
             b->release();
         h_sky.release();
         h_order.release();
@@ -280,6 +280,7 @@ struct Timed {
 
 struct ChunkBufs {
     int64_t *g0, *dg, *Y;
+    int32_t *rowt;
     int2 *win;
     unsigned long long *colmax;
     uint32_t *wq;
@@ -294,6 +295,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     fh_status s;
     if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
+    if ((s = ctx->cur->rowt.ensure((size_t)4 * kTileRows * N, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
@@ -307,6 +309,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->err.ensure(4, st))) return s;
     b.g0 = (int64_t *)ctx->cur->g0.ptr;
     b.dg = (int64_t *)ctx->cur->dg.ptr;
+    b.rowt = (int32_t *)ctx->cur->rowt.ptr;
     b.Y = (int64_t *)ctx->cur->Y.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
     b.colmax = (unsigned long long *)ctx->cur->colmax.ptr;
@@ -336,6 +339,7 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.Y = b.Y;
     a.win = b.win;
     a.dg = b.dg;
+    a.rowt = b.rowt;
     a.wq = weighted ? b.wq : nullptr;
     a.ws = weighted ? b.ws : nullptr;
     a.ws_stride = ws_stride;
@@ -364,6 +368,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                         const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
     HIP_OK(launch_shifts(pm->n_fft, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.g0, b.dg, st));
+    HIP_OK(launch_row_terms(pm->n_fft, b.dg, b.rowt, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
@@ -859,7 +864,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky, (uint64_t)(uintptr_t)b.order,
-        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg};
+        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt};
     fh_ctx::GraphEntry *ge = nullptr;
     for (auto &e : ctx->graphs)
         if (e.key == key) ge = &e;
