@@ -12,16 +12,16 @@
  * level candidates").
  *
  * Exact integer definition (shared by every entry point), stripe edges in
- * units of Q = 2^-18 fine bins:
- *   tau_i = t_i - t0;  S = (K_f * T_FFT) * 2^18
+ * units of Q = 2^-16 fine bins:
+ *   tau_i = t_i - t0;  S = (K_f * T_FFT) * 2^16
  *   G0_i  = llrint((fdot0 * tau_i) * S);   dG_i = llrint((dfdot * tau_i) * S)
  *   D     = 1 + ((vx*nx + vy*ny) + vz*nz);  r = 1 / D        (IEEE binary64,
- *   X     = floor(((double)(K_f * k) * r) * 2^18)             no FMA contraction)
- *   L_s   = X - b0*2^18 - K_f*2^17 - G0_i - s*dG_i
+ *   X     = floor(((double)(K_f * k) * r) * 2^16)             no FMA contraction)
+ *   L_s   = X - b0*2^16 - K_f*2^15 - G0_i - s*dG_i
  *   fine bin b (0 <= b < nf) of row s (0 <= s < ns) gains w_i for peak (i, k)
- *   iff L_s <= b*2^18 < L_s + K_f*2^18.
+ *   iff L_s <= b*2^16 < L_s + K_f*2^16.
  *   Bin b is labelled f0 = (b0 + b) / (K_f T_FFT); row s is fdot0 + s*dfdot.
- *   A grid whose largest step |dfdot tau_i| K_f T_FFT exceeds about 100 fine
+ *   A grid whose largest step |dfdot tau_i| K_f T_FFT exceeds about 400 fine
  *   bins per row is rejected with FH_E_UNSUPPORTED (the tiles keep stripe
  *   edges in 32 bits).
  *

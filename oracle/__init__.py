@@ -110,7 +110,7 @@ def set_threads(n: int) -> None:
 
 
 def shifts(pm, grid):
-    """(G0, dG) int64 per FFT, in fixed-point fine bins (2^18 steps per bin)."""
+    """(G0, dG) int64 per FFT, in fixed-point fine bins (2^16 steps per bin)."""
     lib = _load()
     n = pm.t.shape[0]
     g0 = np.zeros(n, np.int64)

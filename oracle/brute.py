@@ -7,7 +7,7 @@ instead of peak-major) and written independently in Python floats/ints, which
 are IEEE binary64 with round-half-even ``round`` and exact ``math.floor``.
 
 Definitions (Eqs. fdopp, uno, due, ncount, ncountadap, freqres, sdstep), with
-Q = 2^18 fixed-point steps per fine bin:
+Q = 2^16 fixed-point steps per fine bin:
   S = (K_f T_FFT) Q; G0_i = rint((fdot0 tau_i) S); dG_i = rint((dfdot tau_i) S)
   r_i = 1 / (1 + ((v_x n_x + v_y n_y) + v_z n_z))
   X = floor((K_f k r_i) Q); L_s = X - b0 Q - K_f Q/2 - G0_i - s dG_i
@@ -17,8 +17,8 @@ from __future__ import annotations
 
 import math
 
-QD = 262144.0
-QI = 1 << 18
+QD = 65536.0
+QI = 1 << 16
 
 
 def _fft_terms(t_i, t0, t_fft, kf, fdot0, dfdot):

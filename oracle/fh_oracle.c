@@ -18,7 +18,7 @@
  *                                                     (Eqs. ncount, ncountadap)
  *
  * The stripe edge is evaluated in an exactly specified fixed point with
- * Q = 2^18 steps per fine bin, so that integer maps can be compared bit for
+ * Q = 2^16 steps per fine bin, so that integer maps can be compared bit for
  * bit:
  *   S      = (K_f * T_FFT) * Q
  *   G0_i   = llrint((fdot0 * tau_i) * S),  dG_i = llrint((dfdot * tau_i) * S)
@@ -39,8 +39,8 @@
 #include <string.h>
 
 /* fixed-point steps per fine bin */
-#define QD 262144.0
-#define QI ((int64_t)1 << 18)
+#define QD 65536.0
+#define QI ((int64_t)1 << 16)
 
 /* floor(a / Q) for any int64 a, written without relying on >> of negatives */
 static int64_t floor_div_q(int64_t a)

@@ -16,6 +16,16 @@ constexpr int kTileRows = 16;
 constexpr int kRowBlocksPerGroup = 4;
 // Threads per tile workgroup (16 waves).
 constexpr int kTileThreads = 1024;
+constexpr int kTileWaves = kTileThreads / 64;
+// FFTs per tile wave and the padded FFT count of a window row: every wave of
+// a tile takes the same number of FFTs, a multiple of 12 (blocks of four FFTs
+// in a ring of three blocks), and the window entries past the last FFT are
+// empty.
+__host__ __device__ inline int32_t wave_ffts(int32_t n_fft) {
+    const int32_t per = (n_fft + kTileWaves - 1) / kTileWaves;
+    return (per + 11) / 12 * 12;
+}
+__host__ __device__ inline int32_t win_stride(int32_t n_fft) { return kTileWaves * wave_ffts(n_fft); }
 // LDS bytes available to one tile workgroup on gfx950.
 constexpr int kLdsBytes = 163840;
 // Bytes of LDS reserved for the scheduler slot and alignment.
@@ -47,9 +57,9 @@ struct TileArgs {
     int32_t kf, nf, ns, W;        // W: fine bins per tile
     int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
     int32_t n_slots;              // sky directions in this chunk
-    const int64_t *Y;             // [slot][P] stripe edges (2^-18 fine bins, see prep kernel)
-    const int2 *win;              // [slot][nrbg][nbb][N] peak windows
-    const int64_t *dg;            // [N] row step of the stripe edge (2^-18 fine bins)
+    const int64_t *Y;             // [slot][P] stripe edges (2^-16 fine bins, see prep kernel)
+    const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] peak windows
+    const int64_t *dg;            // [N] row step of the stripe edge (2^-16 fine bins)
     const int32_t *rowt;          // [N][16] row terms -j dG_i mod 2^32, j < 16
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
     const WeightStats *ws;        // [slot * ws_stride] or nullptr

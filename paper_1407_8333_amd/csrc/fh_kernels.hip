@@ -32,8 +32,8 @@ namespace fh {
 namespace {
 
 // Fixed point of stripe edges: kQ = 2^kFrac steps per fine bin.
-constexpr int kFrac = 18;
-constexpr double kQd = 262144.0;
+constexpr int kFrac = 16;
+constexpr double kQd = 65536.0;
 constexpr int64_t kQ = (int64_t)1 << kFrac;
 
 __device__ __forceinline__ int64_t shrq(int64_t a) { return a >> kFrac; }  // floor(a / kQ)
@@ -43,13 +43,13 @@ __device__ __forceinline__ int64_t shrq(int64_t a) { return a >> kFrac; }  // fl
 // memory).
 constexpr int64_t kYSentinel = (int64_t)1 << 61;
 
-// Tile-relative edges are 32-bit: with kFrac fractional bits a column must
-// stay inside +-2^(31 - kFrac) = +-8192.  A peak of a window starts within
-// 64 rows' worth of spin-down steps of the tile (the window covers a group of
+// Tile-relative edges are 32-bit: with kFrac = 16 fractional bits a column is
+// the upper half-word, inside +-2^15.  A peak of a window starts within 64
+// rows' worth of spin-down steps of the tile (the window covers a group of
 // 64 rows, the last row block may reach 16 rows past the grid), so
-// max_tile_bins bounds W + K_f + 80 (step + 1) + 64 below 8192.  kFarEdge
-// (6144 bins) then stays in range and beyond the dump column for every row.
-constexpr uint32_t kFarEdge = 6144u << kFrac;
+// max_tile_bins bounds W + K_f + 80 (step + 1) + 64 below 2^15.  kFarEdge
+// (16384 bins) then stays in range and beyond the dump column for every row.
+constexpr uint32_t kFarEdge = 16384u << kFrac;
 
 // ----------------------------------------------------------------------------
 // fills (graph-safe replacements for memset)
@@ -198,11 +198,17 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
                           const int64_t *__restrict__ Y, int64_t n_peaks,
                           const int64_t *__restrict__ dg, int32_t ns, int32_t nrbg, int32_t nbb,
                           int32_t W, int32_t kf, int2 *__restrict__ win) {
+    const int32_t n_pad = win_stride(n_fft);
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)nbb * n_fft) return;
-    const int32_t jb = (int32_t)(idx / n_fft);
-    const int32_t i = (int32_t)(idx - (int64_t)jb * n_fft);
+    if (idx >= (int64_t)nbb * n_pad) return;
+    const int32_t jb = (int32_t)(idx / n_pad);
+    const int32_t i = (int32_t)(idx - (int64_t)jb * n_pad);
     const int32_t g = blockIdx.y, slot = blockIdx.z;
+    int2 *out = win + (((int64_t)slot * nrbg + g) * nbb + jb) * n_pad + i;
+    if (i >= n_fft) {  // padding: empty window
+        *out = make_int2(0, 0);
+        return;
+    }
     const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
     int32_t s_hi = s_lo + kRowBlocksPerGroup * kTileRows - 1;
     if (s_hi > ns - 1) s_hi = ns - 1;
@@ -231,7 +237,7 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
         int64_t cmin = c1 < c2 ? c1 : c2;
         if (cmin >= wc) b = m; else a = m + 1;
     }
-    win[(((int64_t)slot * nrbg + g) * nbb + jb) * n_fft + i] = make_int2((int)lo, (int)a);
+    *out = make_int2((int)lo, (int)a);
 }
 
 // Same windows by one sweep over each FFT's peaks (one wave per FFT, every
@@ -254,14 +260,20 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int slot = blockIdx.y;
-    if (i >= n_fft) return;
+    const int32_t n_pad = win_stride(n_fft);
+    if (i >= n_pad) return;
+    if (i >= n_fft) {  // padding: empty windows
+        for (int e = lane; e < nrbg * nbb; e += 64)
+            win[((int64_t)slot * nrbg * nbb + e) * n_pad + i] = make_int2(0, 0);
+        return;
+    }
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int p0 = (int)(offsets[i] + (int64_t)kYPad * i);
     const int p1 = (int)(offsets[i + 1] + (int64_t)kYPad * i);
     const int64_t dG = dg[i];
     const float inv_w = 1.0f / (float)W;
     for (int g = 0; g < nrbg; ++g) {
-        int2 *wg = win + ((int64_t)slot * nrbg + g) * nbb * (int64_t)n_fft + i;
+        int2 *wg = win + ((int64_t)slot * nrbg + g) * nbb * (int64_t)n_pad + i;
         const int s_lo = g * kRowBlocksPerGroup * kTileRows;
         const int s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
         const int64_t q_lo = (int64_t)s_lo * dG, q_hi = (int64_t)s_hi * dG;
@@ -284,16 +296,16 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
                 before_lo = prev_lo;
             }
             if (p < p1) {
-                for (int jb = before_hi + 1; jb <= jhi; ++jb) wg[(int64_t)jb * n_fft].x = p;
-                for (int jb = before_lo; jb < jlo; ++jb) wg[(int64_t)jb * n_fft].y = p;
+                for (int jb = before_hi + 1; jb <= jhi; ++jb) wg[(int64_t)jb * n_pad].x = p;
+                for (int jb = before_lo; jb < jlo; ++jb) wg[(int64_t)jb * n_pad].y = p;
             }
             const int last = min(63, p1 - 1 - pb);
             prev_hi = __shfl(jhi, last);
             prev_lo = __shfl(jlo, last);
         }
         // bin blocks past the last peak's reach end at the segment end
-        for (int jb = prev_hi + 1 + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_fft].x = p1;
-        for (int jb = prev_lo + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_fft].y = p1;
+        for (int jb = prev_hi + 1 + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_pad].x = p1;
+        for (int jb = prev_lo + lane; jb < nbb; jb += 64) wg[(int64_t)jb * n_pad].y = p1;
     }
 }
 
@@ -318,8 +330,10 @@ __device__ __forceinline__ void stripe_step(uint32_t v, uint32_t t, uint32_t dum
                                             uint32_t lane_off, uint32_t val,
                                             uint32_t *__restrict__ lds) {
     const uint32_t b = __builtin_amdgcn_update_dpp(0u, v, 0x150 + U, 0xF, 0xF, true);
-    const uint32_t col = (uint32_t)((int32_t)(b + t) >> kFrac);
-    const uint32_t cu = col < dump ? col : dump;
+    // the column is the upper half-word (negative columns read as 2^15 and
+    // more); one SDWA min takes it and clamps it to the dump column
+    const uint16_t col = (uint16_t)((b + t) >> kFrac);
+    const uint32_t cu = col < (uint16_t)dump ? col : (uint16_t)dump;
     atomicAdd(lds + cu * kTileRows + lane_off, val);
 }
 
@@ -393,7 +407,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const int s0 = rb * kTileRows;
     const int32_t c0 = jb * W - (kf - 1);
     const int g = rb / kRowBlocksPerGroup;
-    const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * A.n_fft;
+    const int32_t n_pad = win_stride(A.n_fft);
+    const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * n_pad;
     // low 32 bits of the stripe edges (all the tile needs: see stripe_step)
     const uint32_t *__restrict__ Ylo =
         reinterpret_cast<const uint32_t *>(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
@@ -406,46 +421,48 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     const uint32_t below = (1u << j) - 1u;           // pattern lanes below j
     const uint32_t mtab = chunk_pattern(lane);       // lane n holds m(n), n <= 16
 
-    // Each wave takes a contiguous run of FFTs, four at a time (one per lane
-    // group).  A block's window data are loaded two blocks ahead and its
-    // stripe edges one block ahead (a ring of three blocks), so that the
-    // accumulation of a block never waits for memory.  Every load is issued
-    // on every path (clamped to the wave's last FFT) so that the wait counts
-    // stay exact.
-    int per = (A.n_fft + nwave - 1) / nwave;
-    per = (per + 3) & ~3;
-    const int i_begin = min(A.n_fft, wave * per);
-    const int i_end = min(A.n_fft, i_begin + per);
-    const int nblk = (i_end - i_begin + 3) >> 2;
+    // Each wave takes a run of wave_ffts(N) FFTs, four at a time (one per
+    // lane group; windows past the last FFT are empty).  A block's window
+    // data are loaded two blocks ahead and its stripe edges one block ahead
+    // (a ring of three blocks), so that the accumulation of a block never
+    // waits for memory.  Every load is issued on every path so that the wait
+    // counts stay exact.
+    const int per = wave_ffts(A.n_fft);
+    const int i_begin = wave * per;
+    const int nblk = per >> 2;
+    const int i_last = A.n_fft - 1;
 
-    // window data of block bb (stage 1)
+    // window data of block bb (stage 1).  The ring prefetches two blocks past
+    // the wave's last one (never consumed); those reads stay inside the
+    // window row.
     auto stage_w = [&](Quad &Q, int bb) {
-        const int f = i_begin + 4 * bb + grp;
-        const int fc = min(f, i_end - 1);
-        const int2 w2 = win[fc];
+        const uint32_t f = (uint32_t)(i_begin + 4 * bb + grp);
+        const uint32_t fc = min(f, (uint32_t)i_last);
+        const int2 w2 = win[min(f, (uint32_t)(n_pad - 1))];
         Q.lo = w2.x;
-        Q.hi = f < i_end ? w2.y : w2.x;
-        Q.t = (uint32_t)A.rowt[(int64_t)fc * kTileRows + j];
-        Q.dg = dg32[2 * (int64_t)fc];
+        Q.hi = w2.y;
+        Q.t = (uint32_t)A.rowt[fc * kTileRows + (uint32_t)j];
+        Q.dg = dg32[2u * fc];
         Q.wq = WEIGHTED ? wq[fc] : 1u;
     };
     // stripe edges of block bb (stage 2): the chunk sizes follow the largest
     // window of the four groups
     auto stage_y = [&](Quad &Q) {
         Q.cnt = Q.hi - Q.lo;
-        const int c0_ = __builtin_amdgcn_readlane(Q.cnt, 0);
-        const int c1_ = __builtin_amdgcn_readlane(Q.cnt, 16);
-        const int c2_ = __builtin_amdgcn_readlane(Q.cnt, 32);
-        const int c3_ = __builtin_amdgcn_readlane(Q.cnt, 48);
-        Q.cmax = max(max(c0_, c1_), max(c2_, c3_));
+        // max over the four groups (the count is uniform within a group):
+        // DPP row_bcast:15 then row_bcast:31 leave it in lane 63
+        int x = Q.cnt;
+        x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false));
+        x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false));
+        Q.cmax = __builtin_amdgcn_readlane(x, 63);
         const int n1 = min(Q.cmax, 16);
         const int n2 = min(max(Q.cmax - 16, 0), 16);
         Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
         Q.m2 = __builtin_amdgcn_readlane(mtab, n2);
         Q.q1 = (int32_t)__builtin_popcount(Q.m1 & below);
         Q.q2 = 16 + (int32_t)__builtin_popcount(Q.m2 & below);
-        Q.y0 = Ylo[2 * (int64_t)(Q.lo + Q.q1)];
-        Q.y1 = Ylo[2 * (int64_t)(Q.lo + Q.q2)];
+        Q.y0 = Ylo[2u * (uint32_t)(Q.lo + Q.q1)];
+        Q.y1 = Ylo[2u * (uint32_t)(Q.lo + Q.q2)];
     };
     auto consume = [&](const Quad &Q) {
         const uint32_t base = c0q + (uint32_t)s0 * (uint32_t)Q.dg;
@@ -462,7 +479,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             const uint32_t m = __builtin_amdgcn_readlane(mtab, min(Q.cmax - off, 16));
             const int32_t q = off + (int32_t)__builtin_popcount(m & below);
             uint32_t v = kFarEdge;
-            if (q < Q.cnt) v = Ylo[2 * (int64_t)(Q.lo + q)] - base;
+            if (q < Q.cnt) v = Ylo[2u * (uint32_t)(Q.lo + q)] - base;
             stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
         }
     };
@@ -833,10 +850,10 @@ hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *
                           const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
                           int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st) {
     if (method == 0) {
-        dim3 grid(grid_for((int64_t)nbb * n_fft, 256), nrbg, n_slots);
+        dim3 grid(grid_for((int64_t)nbb * win_stride(n_fft), 256), nrbg, n_slots);
         k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
     } else {
-        dim3 grid((n_fft + 3) / 4, n_slots);
+        dim3 grid((win_stride(n_fft) + 3) / 4, n_slots);
         k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
     }
     return hipGetLastError();

@@ -297,7 +297,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->rowt.ensure((size_t)4 * kTileRows * N, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
-    if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * N, st))) return s;
+    if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * win_stride(N), st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
     if ((s = ctx->cur->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
     if ((s = ctx->cur->ws.ensure(sizeof(WeightStats) * (size_t)slots, st))) return s;
@@ -440,7 +440,7 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
 // more tiles per persistent launch)
 int default_chunk(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
     if (requested > 0) return requested;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft + 8 * (int64_t)g->nf;
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
     const int64_t by_mem = std::max<int64_t>(1, ((int64_t)3 << 30) / std::max<int64_t>(1, per_sky));
     return (int)std::min<int64_t>(by_mem, 256);
 }
@@ -799,7 +799,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->tile_bins = p.W;
     out->n_row_blocks = p.nrb;
     out->n_bin_blocks = p.nbb;
-    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * pm->n_fft +
+    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
@@ -971,7 +971,7 @@ struct Lane {
 // Workspace bytes of one search of `chunk` directions with plan p.
 int64_t search_footprint(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk, int n_sky) {
     const int64_t N = pm->n_fft;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * N +
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
                             8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
     return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
 }
