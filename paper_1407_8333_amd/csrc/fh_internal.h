@@ -68,9 +68,7 @@ struct TileArgs {
     float *map_f32;               // [ns][nf]
     unsigned long long *colmax;   // [slot][nf] packed (value << 32 | ~row)
     // persistent scheduling
-    const int32_t *order;         // tile ids, grouped per XCD queue
-    const int32_t *queue_start;   // [kXcds + 1]
-    int32_t *queue_ctr;           // [kXcds]
+    int32_t *queue_ctr;           // [kXcds] claimed positions of the tile queues
     int32_t tile_base;            // first tile id of a plain launch
 };
 

@@ -312,6 +312,14 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // ----------------------------------------------------------------------------
 // tiles
 
+// Workgroup barrier that orders LDS accesses only: global stores and atomics
+// still in flight are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // LDS tile: word (c, j) = c * 16 + j holds the stripe starts of column c
 // (fine bin jb*W - (K_f-1) + c) in row s0 + j; column W + K_f - 1 is a dump
 // column for updates that fall outside the tile.  The 16 lanes of a group
@@ -402,7 +410,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             for (int y = x; y < nwords; ++y) lds[y] = 0;
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     const int s0 = rb * kTileRows;
     const int32_t c0 = jb * W - (kf - 1);
@@ -501,7 +509,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             consume(qc);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // Row sums: H(x) = sum_{c = x}^{x + K_f - 1} P(c), x in [0, W): the +w at
     // the stripe start and the -w K_f bins later, prefix-summed along the row.
@@ -528,14 +536,23 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             else A.map_i32[(int64_t)s * A.nf + b] = (int32_t)acc;
         }
         if (COLMAX) {
-            unsigned long long key =
-                row_ok ? (((unsigned long long)acc << 32) | (0xFFFFFFFFull - (unsigned)s)) : 0ull;
-#pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) {
-                unsigned long long other = __shfl_xor(key, o);
-                key = other > key ? other : key;
-            }
-            if (j == 0) atomicMax(A.colmax + (int64_t)slot * A.nf + b, key);
+            // largest value over the 16 rows (DPP row_shr prefix max: lane 15
+            // ends with it), then the smallest row holding it (prefix min)
+            const uint32_t a = row_ok ? acc : 0u;
+            uint32_t mx = a;
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x111, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x112, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x114, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x118, 0xF, 0xF, false));
+            const uint32_t top = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x15F, 0xF, 0xF, true);
+            int r = row_ok && a == top ? j : kTileRows;
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x111, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x112, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x114, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x118, 0xF, 0xF, false));
+            if (j == kTileRows - 1)
+                atomicMax(A.colmax + (int64_t)slot * A.nf + b,
+                          ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s0 + r)));
         }
         acc -= P[x * kTileRows];
     }
@@ -556,36 +573,60 @@ __global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
     tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
 }
 
-// Persistent form: one workgroup per CU pops tile ids from the queue of its
-// XCD (workgroups are dispatched round-robin over the 8 XCDs), and steals
-// from the other queues when its own is empty.  Every workgroup leaves the
-// loop once all queues are exhausted.
+// Persistent form.  Tile groups (sky, bin block) are dealt round-robin to
+// kXcds queues (workgroups are dispatched round-robin over the XCDs, so
+// workgroup w serves queue w % 8 and the tiles of one group, which read the
+// same stripe edges, stay in one XCD's L2); a queue holds its groups in order,
+// each with all its row blocks.  Position pos of queue qi is therefore
+// group qi + 8 (pos / nrb), row block pos % nrb.
+__device__ __forceinline__ int queue_len(const TileArgs &A, int qi) {
+    const int groups = A.n_slots * A.nbb;
+    return qi < groups ? A.nrb * ((groups - qi + kXcds - 1) / kXcds) : 0;
+}
+
+__device__ __forceinline__ int queue_tile(const TileArgs &A, int qi, int pos) {
+    const int k = pos / A.nrb, rb = pos - k * A.nrb;
+    const int grp = qi + kXcds * k;
+    const int sl = grp / A.nbb, jb = grp - sl * A.nbb;
+    return (sl * A.nrb + rb) * A.nbb + jb;
+}
+
+// A tile from the first queue, starting at `home`, that is not exhausted; -1
+// when all are.
+__device__ int steal_tile(const TileArgs &A, int home) {
+    for (int k = 0; k < kXcds; ++k) {
+        const int qi = (home + k) % kXcds;
+        const int len = queue_len(A, qi);
+        if (__hip_atomic_load(A.queue_ctr + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
+            continue;
+        const int pos = atomicAdd(A.queue_ctr + qi, 1);
+        if (pos < len) return queue_tile(A, qi, pos);
+    }
+    return -1;
+}
+
+// One workgroup per CU.  The next tile of the home queue is claimed when a
+// tile starts (its counter update overlaps the tile's work) and used when it
+// ends; an exhausted home queue sends the workgroup to the others.  Every
+// workgroup leaves the loop once all queues are exhausted.
 template <bool WEIGHTED, bool MAP, bool COLMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
     extern __shared__ uint32_t lds[];
-    __shared__ int s_tile;
+    __shared__ int s_next[2];
     const int home = blockIdx.x % kXcds;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int t = -1;
-            for (int k = 0; k < kXcds && t < 0; ++k) {
-                const int qi = (home + k) % kXcds;
-                const int len = A.queue_start[qi + 1] - A.queue_start[qi];
-                if (__hip_atomic_load(A.queue_ctr + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
-                    continue;
-                const int pos = atomicAdd(A.queue_ctr + qi, 1);
-                if (pos < len) t = A.order[A.queue_start[qi] + pos];
-            }
-            s_tile = t;
-        }
-        __syncthreads();
-        const int t = s_tile;
-        if (t < 0) break;
+    if (threadIdx.x == 0) s_next[0] = steal_tile(A, home);
+    lds_barrier();
+    int t = s_next[0];
+    for (int it = 0; t >= 0; ++it) {
+        int pos = 0;
+        if (threadIdx.x == 0) pos = atomicAdd(A.queue_ctr + home, 1);
         int slot, rb, jb;
         decode_tile(A, t, slot, rb, jb);
-        // the tile order may cover more directions than this launch holds
-        if (slot < A.n_slots) tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
-        __syncthreads();
+        tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        if (threadIdx.x == 0)
+            s_next[(it + 1) & 1] = pos < queue_len(A, home) ? queue_tile(A, home, pos) : steal_tile(A, home);
+        lds_barrier();
+        t = s_next[(it + 1) & 1];
     }
 }
 

@@ -117,22 +117,18 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, rowt, Y, win, colmax, wq, ws, sky, order, qstart, qctr;
-    PinnedBuf h_sky, h_order;
-    // tile order of the persistent schedule currently held in `order`
-    int64_t order_slots = -1, order_nrb = -1, order_nbb = -1;
+    DevBuf g0, dg, rowt, Y, win, colmax, wq, ws, sky, qctr;
+    PinnedBuf h_sky;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &order, &qstart, &qctr})
+        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &qctr})
             b->release();
         h_sky.release();
-        h_order.release();
-        order_slots = -1;
     }
 };
 
@@ -286,7 +282,7 @@ struct ChunkBufs {
     uint32_t *wq;
     WeightStats *ws;
     double *sky;
-    int32_t *order, *qstart, *qctr, *err;
+    int32_t *qctr, *err;
 };
 
 fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
@@ -302,9 +298,6 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
     if ((s = ctx->cur->ws.ensure(sizeof(WeightStats) * (size_t)slots, st))) return s;
     if ((s = ctx->cur->sky.ensure((size_t)24 * n_sky, st))) return s;
-    if (ctx->cur->order.bytes < (size_t)4 * p.tiles_per_sky * slots) ctx->cur->order_slots = -1;
-    if ((s = ctx->cur->order.ensure((size_t)4 * p.tiles_per_sky * slots, st))) return s;
-    if ((s = ctx->cur->qstart.ensure(4 * (kXcds + 1), st))) return s;
     if ((s = ctx->cur->qctr.ensure(4 * kXcds, st))) return s;
     if ((s = ctx->err.ensure(4, st))) return s;
     b.g0 = (int64_t *)ctx->cur->g0.ptr;
@@ -316,8 +309,6 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     b.wq = (uint32_t *)ctx->cur->wq.ptr;
     b.ws = (WeightStats *)ctx->cur->ws.ptr;
     b.sky = (double *)ctx->cur->sky.ptr;
-    b.order = (int32_t *)ctx->cur->order.ptr;
-    b.qstart = (int32_t *)ctx->cur->qstart.ptr;
     b.qctr = (int32_t *)ctx->cur->qctr.ptr;
     b.err = (int32_t *)ctx->err.ptr;
     return FH_OK;
@@ -344,8 +335,6 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.ws = weighted ? b.ws : nullptr;
     a.ws_stride = ws_stride;
     a.colmax = b.colmax;
-    a.order = b.order;
-    a.queue_start = b.qstart;
     a.queue_ctr = b.qctr;
     return a;
 }
@@ -377,36 +366,6 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                        g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method, st));
-    return FH_OK;
-}
-
-// Tile order of the persistent schedule: tiles sharing (sky, bin block) go to
-// the same XCD queue, so the stripe edges they read stay in that XCD's L2.
-fh_status ensure_order(fh_ctx *ctx, const Plan &p, int slots, const ChunkBufs &b, hipStream_t st) {
-    if (ctx->cur->order_slots == slots && ctx->cur->order_nrb == p.nrb && ctx->cur->order_nbb == p.nbb) return FH_OK;
-    const int64_t n_tiles = p.tiles_per_sky * slots;
-    fh_status s = ctx->cur->h_order.ensure(4 * (size_t)(n_tiles + kXcds + 1), st);
-    if (s) return s;
-    HIP_OK(hipStreamSynchronize(st));
-    int32_t *ho = (int32_t *)ctx->cur->h_order.ptr;
-    std::vector<std::vector<int32_t>> q(kXcds);
-    int64_t grp = 0;
-    for (int sl = 0; sl < slots; ++sl)
-        for (int jb = 0; jb < p.nbb; ++jb, ++grp)
-            for (int rb = 0; rb < p.nrb; ++rb)
-                q[grp % kXcds].push_back((int32_t)(((int64_t)sl * p.nrb + rb) * p.nbb + jb));
-    int32_t *hs = ho + n_tiles;
-    int64_t pos = 0;
-    for (int x = 0; x < kXcds; ++x) {
-        hs[x] = (int32_t)pos;
-        for (int32_t t : q[x]) ho[pos++] = t;
-    }
-    hs[kXcds] = (int32_t)pos;
-    HIP_OK(hipMemcpyAsync(b.order, ho, 4 * (size_t)n_tiles, hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(b.qstart, hs, 4 * (kXcds + 1), hipMemcpyHostToDevice, st));
-    ctx->cur->order_slots = slots;
-    ctx->cur->order_nrb = p.nrb;
-    ctx->cur->order_nbb = p.nbb;
     return FH_OK;
 }
 
@@ -460,10 +419,8 @@ fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const 
         TileArgs a = tile_args(pm, g, p, slots, b, weighted, w_stride == 0 ? 0 : 1);
         const int64_t n_tiles = p.tiles_per_sky * slots;
         if (schedule == FH_SCHED_PERSISTENT) {
-            // one tile order for every chunk; tiles of absent directions are skipped
-            if ((s = ensure_order(ctx, p, chunk, b, st))) return s;
             HIP_OK(launch_fill_i32(b.qctr, kXcds, 0, st));
-            const int grid_blocks = (int)std::min<int64_t>(ctx->n_cu, p.tiles_per_sky * chunk);
+            const int grid_blocks = (int)std::min<int64_t>(ctx->n_cu, n_tiles);
             Timed timed(ctx, st, kSpanTiles);
             HIP_OK(launch_tiles(a, weighted, false, true, true, (int32_t)n_tiles, grid_blocks, st));
         } else {
@@ -854,7 +811,6 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
     // hipGraph: capture the whole search once, replay it while every argument
     // and workspace pointer it bakes in is unchanged (sky vectors and weights
     // are read from device memory at replay time, so their contents may change).
-    if (o.schedule == FH_SCHED_PERSISTENT && (s = ensure_order(ctx, p, chunk, b, st))) return s;
     auto bits = [](double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; };
     std::vector<uint64_t> key = {
         (uint64_t)(uintptr_t)pm, (uint64_t)g->kf, (uint64_t)g->b0, (uint64_t)g->nf, (uint64_t)g->ns,
@@ -863,8 +819,9 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)chunk, (uint64_t)n_sky, (uint64_t)(uintptr_t)d_w, (uint64_t)(uint32_t)w_stride,
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
-        (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky, (uint64_t)(uintptr_t)b.order,
-        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt};
+        (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
+        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt,
+        (uint64_t)(uintptr_t)b.qctr};
     fh_ctx::GraphEntry *ge = nullptr;
     for (auto &e : ctx->graphs)
         if (e.key == key) ge = &e;
