@@ -156,8 +156,10 @@ fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
 
 /* Tuning knobs of a context, for experiments and tests.  Results never
  * depend on them.  Names: "window_method" (0 = two binary searches per peak
- * window, 1 = one sweep per FFT, default 1).  FH_E_INVALID for an unknown
- * name or value. */
+ * window, 1 = one sweep per FFT, 2 = stripe edges and windows in one kernel
+ * with the edges of a few FFTs staged in LDS, default 2; it falls back to 1
+ * when one FFT holds too many peaks for the LDS).  FH_E_INVALID for an
+ * unknown name or value. */
 fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value);
 
 /* ---- peakmaps ---------------------------------------------------------- */

@@ -84,6 +84,17 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
                        const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st);
+// fused stripe edges + weights + windows (LDS-staged edges of F FFTs per
+// workgroup); F = front_ffts_per_block(max peaks of one FFT), 0 when even one
+// FFT's edges do not fit (then use launch_prep + launch_windows)
+constexpr int kFrontLdsBytes = 48 * 1024;
+int front_ffts_per_block(int32_t max_per_fft);
+hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
+                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
+                        const int64_t *g0, const int64_t *dg, int64_t *Y, const float *w,
+                        int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
+                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int2 *win,
+                        hipStream_t st);
 // method 0: two binary searches per entry; 1: one sweep per FFT
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
                           const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,

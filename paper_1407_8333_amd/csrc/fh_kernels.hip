@@ -188,6 +188,100 @@ __global__ void __launch_bounds__(256) k_prep(
 }
 
 // ----------------------------------------------------------------------------
+// Fused front: for one direction slot and F consecutive FFTs f0 .. f0+F-1
+// (grid.x over the padded FFT count, grid.y = slot), the stripe edges of
+// their peaks (written out for the tiles and staged in LDS), their
+// fixed-point weights, and every window entry (row group, bin block, FFT) by
+// two binary searches over the staged edges.  The window of a tile is the run
+// of peaks p with
+//   max_s a_s(p) >= jb W - (K_f - 1)   and   min_s a_s(p) < (jb + 1) W
+// over the group's rows s (a_s is monotone in Y, Y ascending within an FFT).
+// Consecutive threads write consecutive FFTs of a window row.
+
+__global__ void __launch_bounds__(256) k_front(
+    int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ bins, const double *__restrict__ v,
+    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
+    const int64_t *__restrict__ dg, int64_t *__restrict__ Y, const float *__restrict__ w,
+    int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
+    uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
+    int2 *__restrict__ win) {
+    extern __shared__ int64_t ys[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int slot = blockIdx.y;
+    const int f0 = blockIdx.x * F;
+    const int fe = min(f0 + F, n_fft);
+    const int32_t n_pad = win_stride(n_fft);
+    int64_t *Yslot = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
+    // padded index of the first staged edge
+    const int64_t pb = f0 < n_fft ? offsets[f0] + (int64_t)kYPad * f0 : 0;
+
+    // stripe edges (as k_prep) and weights, one wave per FFT
+    const double *n = sky + 3 * (int64_t)slot;
+    for (int i = f0 + wave; i < fe; i += 4) {
+        const double *vi = v + 3 * (int64_t)i;
+        double d = vi[0] * n[0];
+        d = d + vi[1] * n[1];
+        d = d + vi[2] * n[2];
+        d = 1.0 + d;
+        const double r = 1.0 / d;
+        const int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+        int64_t *Ys = Yslot + (int64_t)kYPad * i;
+        const int64_t st = (int64_t)kYPad * i - pb;
+        const int64_t e = offsets[i + 1];
+        for (int64_t p = offsets[i] + lane; p < e; p += 64) {
+            double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
+            x = x * kQd;
+            const int64_t y = (int64_t)floor(x) + c;
+            Ys[p] = y;
+            ys[p + st] = y;
+        }
+        if (lane < kYPad) Ys[e + lane] = kYSentinel;
+        if (w != nullptr && lane == 0) {
+            const WeightStats wst = ws[(int64_t)slot * ws_stride];
+            double wi = (double)w[(int64_t)slot * w_stride + i];
+            wq[(int64_t)slot * n_fft + i] = wst.bad ? 0u : (uint32_t)rint(ldexp(wi, wst.frac_bits));
+        }
+    }
+    __syncthreads();
+
+    const int n_entries = nrbg * nbb * F;
+    for (int e = threadIdx.x; e < n_entries; e += blockDim.x) {
+        const int fl = e % F;
+        const int rest = e / F;
+        const int jb = rest % nbb;
+        const int g = rest / nbb;
+        const int f = f0 + fl;
+        int2 out = make_int2(0, 0);
+        if (f < n_fft) {
+            const int64_t p0 = offsets[f] + (int64_t)kYPad * f - pb;
+            const int64_t p1 = offsets[f + 1] + (int64_t)kYPad * f - pb;
+            const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
+            const int32_t s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
+            const int64_t q_lo = (int64_t)s_lo * dg[f], q_hi = (int64_t)s_hi * dg[f];
+            const int64_t t_lo = (int64_t)jb * W - (kf - 1);
+            const int64_t t_hi = (int64_t)(jb + 1) * W;
+            int64_t a = p0, b = p1;
+            while (a < b) {  // first peak whose larger stripe start reaches t_lo
+                const int64_t m = (a + b) >> 1;
+                const int64_t c1 = shrq(ys[m] - q_lo), c2 = shrq(ys[m] - q_hi);
+                if ((c1 > c2 ? c1 : c2) >= t_lo) b = m; else a = m + 1;
+            }
+            const int64_t lo = a;
+            b = p1;
+            while (a < b) {  // first peak whose smaller stripe start reaches t_hi
+                const int64_t m = (a + b) >> 1;
+                const int64_t c1 = shrq(ys[m] - q_lo), c2 = shrq(ys[m] - q_hi);
+                if ((c1 < c2 ? c1 : c2) >= t_hi) b = m; else a = m + 1;
+            }
+            out = make_int2((int)(lo + pb), (int)(a + pb));
+        }
+        win[(((int64_t)slot * nrbg + g) * nbb + jb) * n_pad + f] = out;
+    }
+}
+
+// ----------------------------------------------------------------------------
 // peak windows.  A peak reaches tile (row group g, bin block jb) when its
 // stripe start, over the group's rows, meets the tile's LDS columns
 // [0, W + K_f - 1) measured from fine bin jb*W - (K_f - 1).  Stripe starts are
@@ -884,6 +978,25 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
     dim3 grid((n_fft + 3) / 4, n_slots);
     k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, Y, w, w_stride,
                                  ws, ws_stride, wq);
+    return hipGetLastError();
+}
+
+int front_ffts_per_block(int32_t max_per_fft) {
+    for (int F = 16; F >= 1; F >>= 1)
+        if ((int64_t)F * (max_per_fft + kYPad) * 8 <= kFrontLdsBytes) return F;
+    return 0;
+}
+
+hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
+                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
+                        const int64_t *g0, const int64_t *dg, int64_t *Y, const float *w,
+                        int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
+                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int2 *win,
+                        hipStream_t st) {
+    if (F < 1 || win_stride(n_fft) % F != 0) return hipErrorInvalidValue;
+    dim3 grid(win_stride(n_fft) / F, n_slots);
+    k_front<<<grid, 256, kFrontLdsBytes, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
+                                               w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win);
     return hipGetLastError();
 }
 

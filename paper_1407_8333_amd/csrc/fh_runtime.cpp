@@ -137,7 +137,7 @@ struct fh_ctx {
     int32_t n_cu = 256;
     Workspace main_ws;
     Workspace *cur = &main_ws;  // workspace used by the launch sequences
-    int32_t window_method = 1;  // peak windows: 0 binary searches, 1 sweep
+    int32_t window_method = 2;  // peak windows: 0 binary searches, 1 sweep, 2 fused front
     DevBuf err;
     // autotuned tile width per problem shape
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
@@ -362,10 +362,17 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
         HIP_OK(launch_weight_stats(pm->n_fft, n_vec, d_w, w_stride, pm->adjacent ? 2 : 1, b.ws, b.err, st));
+    const int F = ctx->window_method == 2 ? front_ffts_per_block(pm->max_per_fft) : 0;
+    if (F > 0) {
+        HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
+                            g->b0, b.g0, b.dg, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
+                            p.nrbg, p.nbb, p.W, F, b.win, st));
+        return FH_OK;
+    }
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
                        g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
-                          p.W, g->kf, slots, b.win, ctx->window_method, st));
+                          p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
     return FH_OK;
 }
 
@@ -548,7 +555,7 @@ fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value) {
     if ((s = check_ctx(ctx))) return s;
     if (!name) return fail(FH_E_INVALID, "option name is NULL");
     if (std::strcmp(name, "window_method") == 0) {
-        if (value != 0 && value != 1) return fail(FH_E_INVALID, "window_method must be 0 or 1");
+        if (value < 0 || value > 2) return fail(FH_E_INVALID, "window_method must be 0, 1 or 2");
         ctx->window_method = (int32_t)value;
         return FH_OK;
     }

@@ -244,16 +244,18 @@ def test_graph_replays_match_eager(ctx):
 
 
 def test_window_methods_agree(ctx):
-    """Binary-search and sweep peak windows give identical candidates."""
+    """Binary-search, sweep and fused-front peak windows give identical
+    candidates."""
     import torch
     api = _api()
     w = synth.workload("batch-256hz", n_fft=1500, n_sky=5)
     dpm = ctx.upload(w.pm)
     outs = []
-    for m in (0, 1):
+    for m in (0, 1, 2):
         ctx.set_option("window_method", m)
         outs.append(api.fh_hough_candidates(ctx, dpm, w.sky, w.grid, w.sel, tile_bins=512))
-    ctx.set_option("window_method", 1)
+    ctx.set_option("window_method", 2)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[2])
     dpm.release()
