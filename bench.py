@@ -39,8 +39,8 @@ WORKLOAD_TEXT = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch-256hz")
     ap.add_argument("--n-sky", type=int, default=None)
     ap.add_argument("--plain-sky", type=int, default=64,
@@ -58,6 +58,33 @@ def parse():
                     help="MiB moved by one plain device copy before the timed steps "
                          "(reference dispatch for hardware byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "k_tiles_persistent_batch256hz_hbm_bytes.txt")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_8333_amd", "csrc",
+                             "fh_kernels.hip")
+
+
+def committed_traffic(workload, n_sky, tile_bins, weighted):
+    """HBM bytes per tile launch from the committed rocprofv3 byte counters,
+    when they were taken on this workload and on the current kernel source;
+    None otherwise."""
+    import hashlib
+    if not (workload == "batch-256hz" and n_sky == 1024 and tile_bins == 2496 and weighted):
+        return None
+    try:
+        fields = {}
+        for line in open(TRAFFIC_FILE):
+            if " = " in line:
+                k, v = line.split(" = ", 1)
+                fields[k.strip()] = v.strip()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha256") != src:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def pct(xs, q):
@@ -292,7 +319,7 @@ def main():
                                      "select": prof["select_ms"] / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": LDS_ATOMIC_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / LDS_ATOMIC_PEAK_TOPS,
-                     "traffic": None,
+                     "traffic": committed_traffic(args.workload, n_sky, plan["tile_bins"], wt is not None),
                      "kernel": "k_tiles_persistent (one op = one ds_add_u32 cell update)",
                      "launch_ms": tiles_ms_avg, "cells_per_launch": cells_per_launch},
     }
