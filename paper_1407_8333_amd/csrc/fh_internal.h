@@ -58,7 +58,7 @@ struct TileArgs {
     int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
     int32_t n_slots;              // sky directions in this chunk
     const int64_t *Y;             // [slot][P] stripe edges (2^-16 fine bins, see prep kernel)
-    const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] peak windows
+    const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] sorted windows
     const int64_t *dg;            // [N] row step of the stripe edge (2^-16 fine bins)
     const int32_t *rowt;          // [N][16] row terms -j dG_i mod 2^32, j < 16
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
@@ -95,6 +95,9 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int2 *win,
                         hipStream_t st);
+// window rows sorted by window size per tile-wave run (see k_sort_windows)
+hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t n_slots, const int2 *win,
+                               int2 *wsorted, hipStream_t st);
 // method 0: two binary searches per entry; 1: one sweep per FFT
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
                           const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,

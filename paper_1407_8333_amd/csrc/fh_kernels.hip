@@ -406,6 +406,51 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // ----------------------------------------------------------------------------
 // tiles
 
+// Window rows ordered for the tiles: each tile wave's run of FFTs sorted by
+// window size, largest first (a counting sort over sizes clipped to 127), so
+// that the four FFTs of a tile block have nearly equal windows.  An entry
+// becomes (lo, local << 16 | count), local = the FFT's place in the run.
+// One workgroup per window row (grid.x = row group * bin blocks, grid.y =
+// slot), one wave per run.
+constexpr int kSortBuckets = 128;
+
+__global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, int32_t nrows,
+                                                               const int2 *__restrict__ win,
+                                                               int2 *__restrict__ wsorted) {
+    __shared__ int hist[kTileWaves][kSortBuckets];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = wave_ffts(n_fft);
+    const int64_t row = (int64_t)blockIdx.y * nrows + blockIdx.x;
+    const int2 *src = win + row * win_stride(n_fft) + (int64_t)wave * per;
+    int2 *dst = wsorted + row * win_stride(n_fft) + (int64_t)wave * per;
+    int *h = hist[wave];
+    for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
+    __syncthreads();
+    for (int e = lane; e < per; e += 64) {
+        const int2 w2 = src[e];
+        atomicAdd(&h[kSortBuckets - 1 - min(w2.y - w2.x, kSortBuckets - 1)], 1);
+    }
+    __syncthreads();
+    // exclusive prefix sum over the buckets (lane L holds buckets 2L, 2L+1)
+    const int a0 = h[2 * lane], a1 = h[2 * lane + 1];
+    int incl = a0 + a1;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int excl = incl - (a0 + a1);
+    __syncthreads();
+    h[2 * lane] = excl;
+    h[2 * lane + 1] = excl + a0;
+    __syncthreads();
+    for (int e = lane; e < per; e += 64) {
+        const int2 w2 = src[e];
+        const int c = w2.y - w2.x;
+        const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
+        dst[pos] = make_int2(w2.x, (e << 16) | c);
+    }
+}
+
 // Workgroup barrier that orders LDS accesses only: global stores and atomics
 // still in flight are not waited for.
 __device__ __forceinline__ void lds_barrier() {
@@ -472,7 +517,7 @@ __device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t,
 // (g, j) holds its group's window, row term -j dG and weight, and the stripe
 // edges of its peaks in up to two chunks of 16.
 struct Quad {
-    int lo, hi;          // peak window [lo, hi) of the group's FFT
+    int lo, pk;          // window start; FFT place in the run << 16 | peak count
     int32_t dg;          // row step dG of the group's FFT
     uint32_t t, wq;      // row term -j dG (mod 2^32); fixed-point weight
     int cnt;             // peaks in the window (0 past the wave's run)
@@ -538,25 +583,21 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     // the wave's last one (never consumed); those reads stay inside the
     // window row.
     auto stage_w = [&](Quad &Q, int bb) {
-        const uint32_t f = (uint32_t)(i_begin + 4 * bb + grp);
-        const uint32_t fc = min(f, (uint32_t)i_last);
-        const int2 w2 = win[min(f, (uint32_t)(n_pad - 1))];
+        const uint32_t e = (uint32_t)(i_begin + 4 * bb + grp);
+        const int2 w2 = win[min(e, (uint32_t)(n_pad - 1))];
         Q.lo = w2.x;
-        Q.hi = w2.y;
+        Q.pk = w2.y;
+    };
+    // stripe edges, row terms and weights of block bb (stage 2): the chunk
+    // sizes follow the largest window of the four groups, group 0's (the runs
+    // are sorted by window size)
+    auto stage_y = [&](Quad &Q) {
+        Q.cnt = Q.pk & 0xFFFF;
+        const uint32_t fc = min((uint32_t)(i_begin + (Q.pk >> 16)), (uint32_t)i_last);
         Q.t = (uint32_t)A.rowt[fc * kTileRows + (uint32_t)j];
         Q.dg = dg32[2u * fc];
         Q.wq = WEIGHTED ? wq[fc] : 1u;
-    };
-    // stripe edges of block bb (stage 2): the chunk sizes follow the largest
-    // window of the four groups
-    auto stage_y = [&](Quad &Q) {
-        Q.cnt = Q.hi - Q.lo;
-        // max over the four groups (the count is uniform within a group):
-        // DPP row_bcast:15 then row_bcast:31 leave it in lane 63
-        int x = Q.cnt;
-        x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false));
-        x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false));
-        Q.cmax = __builtin_amdgcn_readlane(x, 63);
+        Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
         const int n2 = min(max(Q.cmax - 16, 0), 16);
         Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
@@ -997,6 +1038,13 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
     dim3 grid(win_stride(n_fft) / F, n_slots);
     k_front<<<grid, 256, kFrontLdsBytes, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
                                                w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t n_slots, const int2 *win,
+                               int2 *wsorted, hipStream_t st) {
+    dim3 grid(nrbg * nbb, n_slots);
+    k_sort_windows<<<grid, kTileThreads, 0, st>>>(n_fft, nrbg * nbb, win, wsorted);
     return hipGetLastError();
 }
 

@@ -117,16 +117,16 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, rowt, Y, win, colmax, wq, ws, sky, qctr;
+    DevBuf g0, dg, rowt, Y, win, wsort, colmax, wq, ws, sky, qctr;
     PinnedBuf h_sky;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &qctr})
+        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &colmax, &wq, &ws, &sky, &qctr})
+        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             b->release();
         h_sky.release();
     }
@@ -209,6 +209,8 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     const double S = (double)g->kf * pm->t_fft;
     const double gmax = (std::fabs(g->fdot0) + std::fabs(g->dfdot) * g->ns) * tau * S;
     if (!(gmax < 1e12)) return fail(FH_E_INVALID, "spin-down shifts exceed the fixed-point range");
+    if (pm->max_per_fft >= 65536)
+        return fail(FH_E_UNSUPPORTED, "an FFT holds %d peaks; at most 65535 are supported", pm->max_per_fft);
     if (max_tile_bins(g->kf, row_step_bins(pm, g)) < 64)
         return fail(FH_E_UNSUPPORTED, "spin-down step of %.6g fine bins per row is too large for a tile",
                     row_step_bins(pm, g));
@@ -277,7 +279,7 @@ struct Timed {
 struct ChunkBufs {
     int64_t *g0, *dg, *Y;
     int32_t *rowt;
-    int2 *win;
+    int2 *win, *wsort;
     unsigned long long *colmax;
     uint32_t *wq;
     WeightStats *ws;
@@ -294,6 +296,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->rowt.ensure((size_t)4 * kTileRows * N, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * win_stride(N), st))) return s;
+    if ((s = ctx->cur->wsort.ensure((size_t)8 * slots * p.nrbg * p.nbb * win_stride(N), st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
     if ((s = ctx->cur->wq.ensure(weighted ? (size_t)4 * slots * N : 4, st))) return s;
     if ((s = ctx->cur->ws.ensure(sizeof(WeightStats) * (size_t)slots, st))) return s;
@@ -305,6 +308,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     b.rowt = (int32_t *)ctx->cur->rowt.ptr;
     b.Y = (int64_t *)ctx->cur->Y.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
+    b.wsort = (int2 *)ctx->cur->wsort.ptr;
     b.colmax = (unsigned long long *)ctx->cur->colmax.ptr;
     b.wq = (uint32_t *)ctx->cur->wq.ptr;
     b.ws = (WeightStats *)ctx->cur->ws.ptr;
@@ -328,7 +332,7 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.nrbg = p.nrbg;
     a.n_slots = slots;
     a.Y = b.Y;
-    a.win = b.win;
+    a.win = b.wsort;
     a.dg = b.dg;
     a.rowt = b.rowt;
     a.wq = weighted ? b.wq : nullptr;
@@ -367,12 +371,14 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
         HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
                             g->b0, b.g0, b.dg, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
                             p.nrbg, p.nbb, p.W, F, b.win, st));
+        HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
         return FH_OK;
     }
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
                        g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
+    HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
     return FH_OK;
 }
 
@@ -406,8 +412,8 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
 // more tiles per persistent launch)
 int default_chunk(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
     if (requested > 0) return requested;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
-    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)3 << 30) / std::max<int64_t>(1, per_sky));
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
+    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)16 << 30) / std::max<int64_t>(1, per_sky));
     return (int)std::min<int64_t>(by_mem, 256);
 }
 
@@ -763,7 +769,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->tile_bins = p.W;
     out->n_row_blocks = p.nrb;
     out->n_bin_blocks = p.nbb;
-    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
+    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
@@ -825,7 +831,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uint32_t)sel->sep, bits(sel->theta), (uint64_t)o.schedule, (uint64_t)p.W,
         (uint64_t)chunk, (uint64_t)n_sky, (uint64_t)(uintptr_t)d_w, (uint64_t)(uint32_t)w_stride,
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
-        (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
+        (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.wsort, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
         (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt,
         (uint64_t)(uintptr_t)b.qctr};
@@ -935,7 +941,7 @@ struct Lane {
 // Workspace bytes of one search of `chunk` directions with plan p.
 int64_t search_footprint(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk, int n_sky) {
     const int64_t N = pm->n_fft;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 8 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
+    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
                             8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
     return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
 }
