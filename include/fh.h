@@ -21,9 +21,10 @@
  *   fine bin b (0 <= b < nf) of row s (0 <= s < ns) gains w_i for peak (i, k)
  *   iff L_s <= b*2^16 < L_s + K_f*2^16.
  *   Bin b is labelled f0 = (b0 + b) / (K_f T_FFT); row s is fdot0 + s*dfdot.
- *   A grid whose largest step |dfdot tau_i| K_f T_FFT exceeds about 400 fine
- *   bins per row is rejected with FH_E_UNSUPPORTED (the tiles keep stripe
- *   edges in 32 bits).
+ *   A grid whose largest step |dfdot tau_i| K_f T_FFT reaches 128 fine bins
+ *   per row is rejected with FH_E_UNSUPPORTED (the tiles keep stripe edges
+ *   in 32 bits and row steps in 24), and so is a peakmap with an FFT of
+ *   65536 peaks or more.
  *
  * Conventions
  *   - Every pointer named d_* is device memory on the context's device and is

@@ -451,6 +451,15 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     }
 }
 
+// Raw buffer access with 32-bit byte offsets (no 64-bit address arithmetic
+// per load); the records limit is never reached by the offsets used here.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ uint32_t ld_u32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
+
 // Workgroup barrier that orders LDS accesses only: global stores and atomics
 // still in flight are not waited for.
 __device__ __forceinline__ void lds_barrier() {
@@ -559,8 +568,6 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     // low 32 bits of the stripe edges (all the tile needs: see stripe_step)
     const uint32_t *__restrict__ Ylo =
         reinterpret_cast<const uint32_t *>(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
-    // low words of the row steps (they fit in 32 bits: see max_tile_bins)
-    const int32_t *__restrict__ dg32 = reinterpret_cast<const int32_t *>(A.dg);
     const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
     const uint32_t dump = (uint32_t)(wc + grp);
     const uint32_t lane_off = (uint32_t)j;
@@ -582,11 +589,13 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     // window data of block bb (stage 1).  The ring prefetches two blocks past
     // the wave's last one (never consumed); those reads stay inside the
     // window row.
+    const __amdgpu_buffer_rsrc_t r_win = buf(win), r_y = buf(Ylo), r_t = buf(A.rowt), r_dg = buf(A.dg);
+    const __amdgpu_buffer_rsrc_t r_wq = buf(WEIGHTED ? (const void *)wq : (const void *)A.dg);
     auto stage_w = [&](Quad &Q, int bb) {
         const uint32_t e = (uint32_t)(i_begin + 4 * bb + grp);
-        const int2 w2 = win[min(e, (uint32_t)(n_pad - 1))];
-        Q.lo = w2.x;
-        Q.pk = w2.y;
+        const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(r_win, min(e, (uint32_t)(n_pad - 1)) * 8u, 0, 0);
+        Q.lo = (int)w2[0];
+        Q.pk = (int)w2[1];
     };
     // stripe edges, row terms and weights of block bb (stage 2): the chunk
     // sizes follow the largest window of the four groups, group 0's (the runs
@@ -594,9 +603,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
     auto stage_y = [&](Quad &Q) {
         Q.cnt = Q.pk & 0xFFFF;
         const uint32_t fc = min((uint32_t)(i_begin + (Q.pk >> 16)), (uint32_t)i_last);
-        Q.t = (uint32_t)A.rowt[fc * kTileRows + (uint32_t)j];
-        Q.dg = dg32[2u * fc];
-        Q.wq = WEIGHTED ? wq[fc] : 1u;
+        Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
+        Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
+        Q.wq = WEIGHTED ? ld_u32(r_wq, fc * 4u) : 1u;
         Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
         const int n2 = min(max(Q.cmax - 16, 0), 16);
@@ -604,11 +613,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
         Q.m2 = __builtin_amdgcn_readlane(mtab, n2);
         Q.q1 = (int32_t)__builtin_popcount(Q.m1 & below);
         Q.q2 = 16 + (int32_t)__builtin_popcount(Q.m2 & below);
-        Q.y0 = Ylo[2u * (uint32_t)(Q.lo + Q.q1)];
-        Q.y1 = Ylo[2u * (uint32_t)(Q.lo + Q.q2)];
+        Q.y0 = ld_u32(r_y, (uint32_t)(Q.lo + Q.q1) * 8u);
+        Q.y1 = ld_u32(r_y, (uint32_t)(Q.lo + Q.q2) * 8u);
     };
     auto consume = [&](const Quad &Q) {
-        const uint32_t base = c0q + (uint32_t)s0 * (uint32_t)Q.dg;
+        const uint32_t base = c0q + (uint32_t)__mul24(s0, Q.dg);  // |dG| < 2^23
         uint32_t val = Q.wq;
         asm volatile("" : "+v"(val));
         const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
@@ -622,7 +631,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, i
             const uint32_t m = __builtin_amdgcn_readlane(mtab, min(Q.cmax - off, 16));
             const int32_t q = off + (int32_t)__builtin_popcount(m & below);
             uint32_t v = kFarEdge;
-            if (q < Q.cnt) v = Ylo[2u * (uint32_t)(Q.lo + q)] - base;
+            if (q < Q.cnt) v = ld_u32(r_y, (uint32_t)(Q.lo + q) * 8u) - base;
             stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
         }
     };
@@ -973,6 +982,8 @@ int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + kDumpCols) 
 int max_tile_bins(int kf, double step_bins) {
     const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dumps
     int w = words - kf + 1 - kDumpCols;                           // W + kf - 1 + dumps <= words
+    // the row base s0 dG is a 24-bit product: |dG| < 2^23 (128 fine bins)
+    if (step_bins * kQd + 1.0 >= 8388608.0) return 0;
     // 32-bit tile-relative edges (see kFarEdge)
     const double m = ceil(step_bins) + 1.0;
     const double wr = (double)(1 << (31 - kFrac)) - 64.0 - kf - 80.0 * m;
