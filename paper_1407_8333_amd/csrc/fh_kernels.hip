@@ -482,23 +482,29 @@ __device__ __forceinline__ void lds_barrier() {
 // [0, W + K_f - 1) (negative ones wrap to large unsigned values) go to the
 // group's dump column.
 template <int U>
-__device__ __forceinline__ void stripe_step(uint32_t v, uint32_t t, uint32_t dump,
-                                            uint32_t lane_off, uint32_t val,
-                                            uint32_t *__restrict__ lds) {
+__device__ __forceinline__ uint32_t stripe_word(uint32_t v, uint32_t t, uint32_t dump, uint32_t lane_off) {
     const uint32_t b = __builtin_amdgcn_update_dpp(0u, v, 0x150 + U, 0xF, 0xF, true);
     // the column is the upper half-word (negative columns read as 2^15 and
     // more); one SDWA min takes it and clamps it to the dump column
     const uint16_t col = (uint16_t)((b + t) >> kFrac);
     const uint32_t cu = col < (uint16_t)dump ? col : (uint16_t)dump;
-    atomicAdd(lds + cu * kTileRows + lane_off, val);
+    return cu * kTileRows + lane_off;
 }
 
+// Steps U .. E-1, two at a time (independent address chains interleave).
 template <int U, int E>
 __device__ __forceinline__ void stripe_run(uint32_t v, uint32_t t, uint32_t dump,
                                            uint32_t lane_off, uint32_t val,
                                            uint32_t *__restrict__ lds) {
-    stripe_step<U>(v, t, dump, lane_off, val, lds);
-    if constexpr (U + 1 < E) stripe_run<U + 1, E>(v, t, dump, lane_off, val, lds);
+    if constexpr (U + 1 < E) {
+        const uint32_t a0 = stripe_word<U>(v, t, dump, lane_off);
+        const uint32_t a1 = stripe_word<U + 1>(v, t, dump, lane_off);
+        atomicAdd(lds + a0, val);
+        atomicAdd(lds + a1, val);
+        stripe_run<U + 2, E>(v, t, dump, lane_off, val, lds);
+    } else if constexpr (U < E) {
+        atomicAdd(lds + stripe_word<U>(v, t, dump, lane_off), val);
+    }
 }
 
 // A chunk of up to 64 peaks of one FFT occupies the lanes named by a 16-bit
