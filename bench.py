@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of one direction the CPU oracle computes (0 = auto)")
-    ap.add_argument("--serve-requests", type=int, default=120,
+    ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the Poisson serving run (0 disables it)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured serving capacity")
@@ -136,7 +136,7 @@ SERVE_BANDS = [(8192.0, 40.0), (8192.0, 110.0), (4096.0, 180.0), (4096.0, 450.0)
                (2048.0, 330.0), (2048.0, 500.0), (1024.0, 700.0), (1024.0, 950.0)]
 
 
-def serve_bench(ctx, n_req, load, seed=77):
+def serve_bench(ctx, n_req, load, lanes=8, seed=77):
     """Poisson stream of (band, sky patch, spin-down range) requests through the
     continuous-batching server; bands are resident 1 Hz peakmaps of a ~149 d
     run with T_FFT chosen by band."""
@@ -162,9 +162,9 @@ def serve_bench(ctx, n_req, load, seed=77):
         sky = synth.sky_uniform(int(rng.integers(1, 257)), rng)
         return dpm, grid, sel, sky
 
-    srv = api.Server(ctx, hbm_budget=48 << 30, lanes=4)
+    srv = api.Server(ctx, hbm_budget=64 << 30, lanes=lanes)
     # capacity: a burst of requests submitted at once
-    burst = [draw() for _ in range(12)]
+    burst = [draw() for _ in range(32)]
     outs = [torch.empty((len(b[3]), api.n_subbands(b[1], b[2]), 2, 8), dtype=torch.int32,
                         device="cuda") for b in burst]
     for b, o in zip(burst, outs):  # first use of each shape: tile autotuning, allocation
@@ -173,10 +173,13 @@ def serve_bench(ctx, n_req, load, seed=77):
     t0 = time.perf_counter()
     for b, o in zip(burst, outs):
         srv.submit(b[0], b[3], b[1], b[2], o)
-    got = 0
+    got, burst_cells = 0, 0
     while got < len(burst):
-        got += len(srv.poll())
-    cap = len(burst) / (time.perf_counter() - t0)
+        for c in srv.poll():
+            got += 1
+            burst_cells += c["cell_updates"]
+    burst_s = time.perf_counter() - t0
+    cap = len(burst) / burst_s
     rate = load * cap
     reqs = [draw() for _ in range(n_req)]
     outs = [torch.empty((len(r[3]), api.n_subbands(r[1], r[2]), 2, 8), dtype=torch.int32,
@@ -198,8 +201,9 @@ def serve_bench(ctx, n_req, load, seed=77):
         d.release()
     lat = [c["latency_ms"] for c in done]
     cells = sum(c["cell_updates"] for c in done)
-    return {"requests": n_req, "lanes": 4, "hbm_budget_gib": 48,
+    return {"requests": n_req, "lanes": lanes, "hbm_budget_gib": 64,
             "arrival_rate_per_s": rate, "capacity_per_s": cap, "load": load,
+            "capacity_throughput": burst_cells / burst_s,
             "p50_latency_ms": pct(lat, 50), "p99_latency_ms": pct(lat, 99),
             "mean_queue_ms": float(np.mean([c["queue_ms"] for c in done])),
             "throughput": cells / wall, "unit": "cell-updates/s",
