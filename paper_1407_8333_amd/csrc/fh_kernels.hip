@@ -260,20 +260,20 @@ __global__ void __launch_bounds__(256) k_front(
             const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
             const int32_t s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
             const int64_t q_lo = (int64_t)s_lo * dg[f], q_hi = (int64_t)s_hi * dg[f];
-            const int64_t t_lo = (int64_t)jb * W - (kf - 1);
-            const int64_t t_hi = (int64_t)(jb + 1) * W;
-            int64_t a = p0, b = p1;
-            while (a < b) {  // first peak whose larger stripe start reaches t_lo
-                const int64_t m = (a + b) >> 1;
-                const int64_t c1 = shrq(ys[m] - q_lo), c2 = shrq(ys[m] - q_hi);
-                if ((c1 > c2 ? c1 : c2) >= t_lo) b = m; else a = m + 1;
+            // max_s a_s = floor((Y - min q) / kQ) >= t  <=>  Y >= t kQ + min q
+            // min_s a_s = floor((Y - max q) / kQ) >= t  <=>  Y >= t kQ + max q
+            const int64_t y_lo = ((int64_t)jb * W - (kf - 1)) * kQ + (q_lo < q_hi ? q_lo : q_hi);
+            const int64_t y_hi = (int64_t)(jb + 1) * W * kQ + (q_lo < q_hi ? q_hi : q_lo);
+            int a = (int)p0, b = (int)p1;
+            while (a < b) {  // first peak with Y >= y_lo
+                const int m = (a + b) >> 1;
+                if (ys[m] >= y_lo) b = m; else a = m + 1;
             }
-            const int64_t lo = a;
-            b = p1;
-            while (a < b) {  // first peak whose smaller stripe start reaches t_hi
-                const int64_t m = (a + b) >> 1;
-                const int64_t c1 = shrq(ys[m] - q_lo), c2 = shrq(ys[m] - q_hi);
-                if ((c1 < c2 ? c1 : c2) >= t_hi) b = m; else a = m + 1;
+            const int lo = a;
+            b = (int)p1;
+            while (a < b) {  // first peak with Y >= y_hi
+                const int m = (a + b) >> 1;
+                if (ys[m] >= y_hi) b = m; else a = m + 1;
             }
             out = make_int2((int)(lo + pb), (int)(a + pb));
         }
