@@ -238,6 +238,56 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky,
                               const fh_grid *grid, const fh_select *sel,
                               const fh_options *opts, fh_candidate *d_out, void *stream);
 
+/* ---- refined grid ---------------------------------------------------- */
+
+/* The peaks of `pm` whose natural bin k lies in [k_lo, k_hi), as a new device
+ * peakmap with the same FFTs, times and velocities (a narrow band for a small
+ * search).  Runs on `stream` and waits for it (the exact peak count is read
+ * back); the new handle is owned by the caller and released with
+ * fh_peakmap_release.  Errors: FH_E_INVALID for k_lo < 0 or k_hi <= k_lo,
+ * FH_E_NOMEM, FH_E_DEVICE (nothing is allocated on failure). */
+fh_status fh_peakmap_slice(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi,
+                           void *stream, fh_peakmap **out);
+
+/* A coarse candidate to refine: frequency f0 [Hz] and spin-down fdot [Hz/s]
+ * at the reference time t0 of fh_refine_opts, ecliptic longitude and latitude
+ * [rad] of its sky point, and the coarse sky spacings there (longitude step of
+ * its ring, latitude distance to the adjacent ring). */
+typedef struct fh_coarse_cand {
+    double f0, fdot, lambda, beta, dlambda, dbeta;
+} fh_coarse_cand;
+
+/* Refinement (Sec. "Refined Grid in the parameter space"): frequency over
+ * K_f fine bins per natural bin, +-1 natural bin around f0 (2 K_f + 1 bins);
+ * spin-down step dfdot / k_fdot with 2 k_fdot steps below fdot and
+ * 2 k_fdot - 1 above (4 k_fdot rows, row 2 k_fdot = fdot); k_sky x k_sky sky
+ * points (k_sky odd) at steps dlambda / k_sky, dbeta / k_sky around the
+ * candidate.  theta is the peakmap threshold used for the critical ratio. */
+typedef struct fh_refine_opts {
+    int32_t kf, k_fdot, k_sky, pad;
+    double dfdot, t0, theta;
+} fh_refine_opts;
+
+/* One refined candidate per coarse one: the best cell over the refined sky
+ * points, frequency bins and spin-down rows (larger value, then smaller sky
+ * index, bin and row); sky = j * k_sky + i for latitude step j and longitude
+ * step i (both from -(k_sky-1)/2); bin and row index the refined grid. */
+typedef struct fh_refined {
+    int32_t cand, sky, bin, row;
+    float value, cr;
+    int32_t valid, pad;
+    double f0, fdot, lambda, beta;
+} fh_refined;
+
+/* Refine n_cand coarse candidates (host array) against `pm`; d_w: NULL or
+ * FP32 weights [N] (shared).  Each candidate is searched on the peaks within
+ * its band plus the Doppler and spin-down margin, so the result equals the
+ * search of the full peakmap.  Writes d_out[n_cand] (device).  FH_E_INVALID
+ * for bad options (kf, k_fdot >= 1, k_sky odd >= 1, dfdot > 0, finite
+ * candidates). */
+fh_status fh_refine(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_cand, const fh_coarse_cand *cands,
+                    const fh_refine_opts *opts, const float *d_w, fh_refined *d_out, void *stream);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /* A continuous-batching request server over one context.  Requests

@@ -69,6 +69,17 @@ class fh_profile(ctypes.Structure):
                 ("graph_launches", ctypes.c_int64)]
 
 
+class fh_coarse_cand(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double), ("fdot", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("beta", ctypes.c_double), ("dlambda", ctypes.c_double), ("dbeta", ctypes.c_double)]
+
+
+class fh_refine_opts(ctypes.Structure):
+    _fields_ = [("kf", ctypes.c_int32), ("k_fdot", ctypes.c_int32), ("k_sky", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("dfdot", ctypes.c_double), ("t0", ctypes.c_double),
+                ("theta", ctypes.c_double)]
+
+
 class fh_request(ctypes.Structure):
     _fields_ = [("pm", ctypes.c_void_p), ("grid", fh_grid), ("sel", fh_select),
                 ("n_sky", ctypes.c_int32), ("sky", ctypes.c_void_p), ("d_w", ctypes.c_void_p),
@@ -104,6 +115,8 @@ _PROTOS = {
     "fh_hough_candidates": ([P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.POINTER(fh_grid),
                              ctypes.POINTER(fh_select), ctypes.POINTER(fh_options), P, P],
                             ctypes.c_int),
+    "fh_peakmap_slice": ([P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)], ctypes.c_int),
+    "fh_refine": ([P, P, ctypes.c_int32, P, ctypes.POINTER(fh_refine_opts), P, P, P], ctypes.c_int),
     "fh_server_create": ([P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)],
                          ctypes.c_int),
     "fh_server_submit": ([P, ctypes.POINTER(fh_request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -182,3 +195,5 @@ fh_ctx_set_option = _fwd("fh_ctx_set_option")
 fh_peakmap_from_spectra = _fwd("fh_peakmap_from_spectra")
 fh_peakmap_download = _fwd("fh_peakmap_download")
 fh_peakmap_shape = _fwd("fh_peakmap_shape")
+fh_peakmap_slice = _fwd("fh_peakmap_slice")
+fh_refine = _fwd("fh_refine")

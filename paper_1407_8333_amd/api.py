@@ -131,7 +131,20 @@ class DevicePeakmap:
         off = np.zeros(self.n_fft + 1, np.int64)
         bins = np.zeros(max(1, self.n_peaks), np.int32)
         check(_lib.fh_peakmap_download(self.ctx.handle, self.handle, off.ctypes.data, bins.ctypes.data))
-        return off, bins[: self.n_peaks]
+        return off, bins[: int(off[-1])]
+
+    def slice(self, k_lo: int, k_hi: int, stream=None) -> "DevicePeakmap":
+        """The peaks with natural bin in [k_lo, k_hi) (fh_peakmap_slice)."""
+        q = DevicePeakmap.__new__(DevicePeakmap)
+        q.ctx = self.ctx
+        h = ctypes.c_void_p()
+        check(_lib.fh_peakmap_slice(self.ctx.handle, self.handle, int(k_lo), int(k_hi), _stream(stream),
+                                    ctypes.byref(h)))
+        q.handle = h
+        n, p = ctypes.c_int32(), ctypes.c_int64()
+        check(_lib.fh_peakmap_shape(h, ctypes.byref(n), ctypes.byref(p)))
+        q.n_fft, q.n_peaks = n.value, p.value
+        return q
 
     @property
     def nbytes(self) -> int:
@@ -149,6 +162,33 @@ class DevicePeakmap:
                 self.release()
         except Exception:
             pass
+
+
+REFINED_DTYPE = np.dtype([("cand", "<i4"), ("sky", "<i4"), ("bin", "<i4"), ("row", "<i4"),
+                          ("value", "<f4"), ("cr", "<f4"), ("valid", "<i4"), ("pad", "<i4"),
+                          ("f0", "<f8"), ("fdot", "<f8"), ("lambda", "<f8"), ("beta", "<f8")])
+
+
+def refine(ctx: Context, dpm: DevicePeakmap, cands, kf: int, k_fdot: int, k_sky: int, dfdot: float,
+           t0: float, theta: float = 2.5, weights: Optional[torch.Tensor] = None, stream=None):
+    """Refined candidates (fh_refine).  cands: array [n, 6] of (f0, fdot,
+    lambda, beta, dlambda, dbeta).  Returns a uint8 device tensor of n
+    fh_refined records; decode with ``decode_refined``."""
+    c = np.ascontiguousarray(np.asarray(cands, dtype=np.float64).reshape(-1, 6))
+    n = c.shape[0]
+    out = torch.empty((max(n, 1) * REFINED_DTYPE.itemsize,), dtype=torch.uint8, device="cuda:%d" % ctx.device)
+    w_ptr = None
+    if weights is not None:
+        assert weights.dtype == torch.float32 and weights.is_cuda and weights.numel() == dpm.n_fft
+        w_ptr = ctypes.c_void_p(weights.data_ptr())
+    o = _lib.fh_refine_opts(int(kf), int(k_fdot), int(k_sky), 0, float(dfdot), float(t0), float(theta))
+    check(_lib.fh_refine(ctx.handle, dpm.handle, n, c.ctypes.data, ctypes.byref(o), w_ptr,
+                         ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out[: n * REFINED_DTYPE.itemsize]
+
+
+def decode_refined(raw: torch.Tensor) -> np.ndarray:
+    return raw.detach().cpu().numpy().view(REFINED_DTYPE)
 
 
 def _nhat(n) -> ctypes.Array:

@@ -115,6 +115,13 @@ hipError_t launch_pm_rows(int32_t n_fft, int32_t n_bins, int64_t ld, const float
 hipError_t launch_pm_scan(int32_t n_fft, const int32_t *counts, int64_t *offsets, hipStream_t st);
 hipError_t launch_pm_pack(int32_t n_fft, int32_t cap, const int32_t *scratch, const int64_t *offsets,
                           int32_t *bins, hipStream_t st);
+// peaks of each FFT with natural bin in [k_lo, k_hi) into a new CSR
+hipError_t launch_slice(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo, int32_t k_hi,
+                        int64_t *first, int32_t *counts, int64_t *out_offsets, int32_t *out_bins,
+                        hipStream_t st);
+// best of the first candidates of each refined direction, per coarse candidate
+hipError_t launch_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate *cands, const double *params,
+                              const double *lamb, fh_refined *out, hipStream_t st);
 int tile_lds_bytes(int W, int kf);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).
 hipError_t init_kernel_attributes();

@@ -1139,6 +1139,97 @@ hipError_t launch_pm_rows(int32_t n_fft, int32_t n_bins, int64_t ld, const float
     return hipGetLastError();
 }
 
+namespace {
+
+// ----------------------------------------------------------------------------
+// peakmap slice: the peaks of each FFT with natural bin in [k_lo, k_hi)
+
+__global__ void k_slice_count(int32_t n_fft, const int64_t *__restrict__ offsets,
+                              const int32_t *__restrict__ bins, int32_t k_lo, int32_t k_hi,
+                              int64_t *__restrict__ first, int32_t *__restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_fft) return;
+    const int64_t p0 = offsets[i], p1 = offsets[i + 1];
+    int64_t a = p0, b = p1;
+    while (a < b) {  // first bin >= k_lo
+        const int64_t m = (a + b) >> 1;
+        if (bins[m] >= k_lo) b = m; else a = m + 1;
+    }
+    const int64_t lo = a;
+    b = p1;
+    while (a < b) {  // first bin >= k_hi
+        const int64_t m = (a + b) >> 1;
+        if (bins[m] >= k_hi) b = m; else a = m + 1;
+    }
+    first[i] = lo;
+    counts[i] = (int32_t)(a - lo);
+}
+
+__global__ void k_slice_pack(const int64_t *__restrict__ first, const int32_t *__restrict__ counts,
+                             const int64_t *__restrict__ offsets, const int32_t *__restrict__ bins,
+                             int32_t *__restrict__ out) {
+    const int i = blockIdx.x;
+    const int64_t src = first[i], dst = offsets[i];
+    for (int k = threadIdx.x; k < counts[i]; k += blockDim.x) out[dst + k] = bins[src + k];
+}
+
+// ----------------------------------------------------------------------------
+// refined candidates: the best of the k_sky^2 directions' first candidates
+
+__global__ void k_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate *__restrict__ cands,
+                              const double *__restrict__ params, const double *__restrict__ lamb,
+                              fh_refined *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    const fh_candidate *cc = cands + (int64_t)c * n_dir * 2;
+    int best = -1;
+    for (int s = 0; s < n_dir; ++s) {
+        const fh_candidate &x = cc[2 * s];
+        if (!x.valid) continue;
+        if (best < 0 || x.value > cc[2 * best].value) best = s;
+    }
+    fh_refined r{};
+    r.cand = c;
+    if (best >= 0) {
+        const fh_candidate &x = cc[2 * best];
+        const double *pr = params + 4 * (int64_t)c;  // f0 of bin 0, bin width, fdot of row 0, row step
+        r.sky = best;
+        r.bin = x.bin;
+        r.row = x.row;
+        r.value = x.value;
+        r.cr = x.cr;
+        r.valid = 1;
+        r.f0 = pr[0] + x.bin * pr[1];
+        r.fdot = pr[2] + x.row * pr[3];
+        r.lambda = lamb[2 * ((int64_t)c * n_dir + best)];
+        r.beta = lamb[2 * ((int64_t)c * n_dir + best) + 1];
+    } else {
+        r.sky = r.bin = r.row = -1;
+    }
+    out[c] = r;
+}
+
+}  // namespace
+
+hipError_t launch_slice(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo, int32_t k_hi,
+                        int64_t *first, int32_t *counts, int64_t *out_offsets, int32_t *out_bins,
+                        hipStream_t st) {
+    k_slice_count<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, offsets, bins, k_lo, k_hi, first, counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pm_scan<<<1, 1024, 0, st>>>(n_fft, counts, out_offsets);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_slice_pack<<<n_fft, 256, 0, st>>>(first, counts, out_offsets, bins, out_bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate *cands, const double *params,
+                              const double *lamb, fh_refined *out, hipStream_t st) {
+    if (n_cand <= 0) return hipSuccess;
+    k_refine_pick<<<grid_for(n_cand, 64), 64, 0, st>>>(n_cand, n_dir, cands, params, lamb, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_pm_scan(int32_t n_fft, const int32_t *counts, int64_t *offsets, hipStream_t st) {
     k_pm_scan<<<1, 1024, 0, st>>>(n_fft, counts, offsets);
     return hipGetLastError();

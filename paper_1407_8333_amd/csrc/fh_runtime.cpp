@@ -139,6 +139,8 @@ struct fh_ctx {
     Workspace *cur = &main_ws;  // workspace used by the launch sequences
     int32_t window_method = 2;  // peak windows: 0 binary searches, 1 sweep, 2 fused front
     DevBuf err;
+    // refinement: sliced peakmap and per-call scratch
+    DevBuf rf_offsets, rf_bins, rf_t, rf_v, rf_first, rf_counts, rf_cands, rf_aux;
     // autotuned tile width per problem shape
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
     // captured searches (fh_options.use_graph), keyed by every argument and
@@ -552,6 +554,9 @@ void fh_ctx_destroy(fh_ctx *ctx) {
     ctx->graphs.clear();
     ctx->main_ws.release();
     ctx->err.release();
+    for (DevBuf *b : {&ctx->rf_offsets, &ctx->rf_bins, &ctx->rf_t, &ctx->rf_v, &ctx->rf_first, &ctx->rf_counts,
+                      &ctx->rf_cands, &ctx->rf_aux})
+        b->release();
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
 }
@@ -756,6 +761,172 @@ void fh_peakmap_release(fh_ctx *ctx, fh_peakmap *pm) {
 }
 
 int64_t fh_peakmap_bytes(const fh_peakmap *pm) { return pm ? pm->bytes : 0; }
+
+fh_status fh_peakmap_slice(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi, void *stream,
+                           fh_peakmap **out) {
+    fh_status s;
+    if (!out) return fail(FH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if (k_lo < 0 || k_hi <= k_lo) return fail(FH_E_INVALID, "need 0 <= k_lo < k_hi");
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t N = pm->n_fft;
+    const int64_t cap = std::min<int64_t>((int64_t)N * (k_hi - k_lo), pm->n_peaks);
+    if ((s = ctx->rf_first.ensure(8 * (size_t)N, st)) || (s = ctx->rf_counts.ensure(4 * (size_t)N, st)))
+        return s;
+    fh_peakmap *q = new fh_peakmap(*pm);
+    q->d_offsets = nullptr;
+    q->d_bins = nullptr;
+    q->d_t = nullptr;
+    q->d_v = nullptr;
+    q->n_peaks = cap;
+    q->k_min = k_lo;
+    q->k_max = k_hi - 1;
+    q->max_per_fft = std::min<int32_t>(pm->max_per_fft, k_hi - k_lo);
+    const size_t b_off = 8 * (size_t)(N + 1), b_bins = 4 * (size_t)std::max<int64_t>(1, cap);
+    if (hipMalloc(&q->d_offsets, b_off) != hipSuccess || hipMalloc(&q->d_bins, b_bins) != hipSuccess ||
+        hipMalloc(&q->d_t, 8 * (size_t)N) != hipSuccess || hipMalloc(&q->d_v, 24 * (size_t)N) != hipSuccess) {
+        fh_peakmap_release(ctx, q);
+        return fail(FH_E_NOMEM, "device allocation for the sliced peakmap failed");
+    }
+    q->bytes = (int64_t)(b_off + b_bins + 32 * (size_t)N);
+    hipError_t e = launch_slice(N, pm->d_offsets, pm->d_bins, k_lo, k_hi, (int64_t *)ctx->rf_first.ptr,
+                                (int32_t *)ctx->rf_counts.ptr, q->d_offsets, q->d_bins, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->d_t, pm->d_t, 8 * (size_t)N, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->d_v, pm->d_v, 24 * (size_t)N, hipMemcpyDeviceToDevice, st);
+    // exact peak count and longest FFT of the slice (the allocation keeps the bound)
+    std::vector<int64_t> h_off((size_t)N + 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_off.data(), q->d_offsets, b_off, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        fh_peakmap_release(ctx, q);
+        return fail(FH_E_DEVICE, "slicing the peakmap failed: %s", hipGetErrorString(e));
+    }
+    q->n_peaks = h_off[N];
+    q->max_per_fft = 0;
+    for (int32_t i = 0; i < N; ++i) q->max_per_fft = std::max<int32_t>(q->max_per_fft, (int32_t)(h_off[i + 1] - h_off[i]));
+    *out = q;
+    return FH_OK;
+}
+
+fh_status fh_refine(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_cand, const fh_coarse_cand *cands,
+                    const fh_refine_opts *o, const float *d_w, fh_refined *d_out, void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm || !o) return fail(FH_E_INVALID, "peakmap or options is NULL");
+    if (n_cand < 0 || (n_cand > 0 && (!cands || !d_out))) return fail(FH_E_INVALID, "bad candidate arrays");
+    if (o->kf < 1 || o->kf > 64 || o->k_fdot < 1 || o->k_sky < 1 || o->k_sky % 2 == 0 || o->k_sky > 63)
+        return fail(FH_E_INVALID, "refine options need 1 <= kf <= 64, k_fdot >= 1, odd 1 <= k_sky <= 63");
+    if (!(o->dfdot > 0) || !std::isfinite(o->dfdot) || !std::isfinite(o->t0) || !(o->theta > 0))
+        return fail(FH_E_INVALID, "refine options need dfdot > 0, finite t0 and theta > 0");
+    if (n_cand == 0) return FH_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int kf = o->kf, ks = o->k_sky, n_dir = ks * ks, L = (ks - 1) / 2;
+    const int ns = 4 * o->k_fdot, nf = 2 * kf + 1;
+    const double T = pm->t_fft, dfd = o->dfdot / o->k_fdot;
+    const double tau = std::max(std::fabs(pm->t_min - o->t0), std::fabs(pm->t_max - o->t0));
+    const double ce = std::cos(23.44 * M_PI / 180.0), se = std::sin(23.44 * M_PI / 180.0);
+    std::vector<fh_grid> grids((size_t)n_cand);
+    std::vector<int32_t> klo((size_t)n_cand), khi((size_t)n_cand);
+    std::vector<double> sky((size_t)n_cand * n_dir * 3), aux((size_t)n_cand * (4 + 2 * n_dir));
+    double *prm = aux.data(), *lamb = aux.data() + 4 * (size_t)n_cand;
+    int32_t width = 1, kmin = 0x7fffffff, kmax = 0;
+    for (int c = 0; c < n_cand; ++c) {
+        const fh_coarse_cand &q = cands[c];
+        if (!std::isfinite(q.f0) || !(q.f0 > 0) || !std::isfinite(q.fdot) || !std::isfinite(q.lambda) ||
+            !std::isfinite(q.beta) || !std::isfinite(q.dlambda) || !std::isfinite(q.dbeta))
+            return fail(FH_E_INVALID, "candidate %d is not finite", c);
+        fh_grid &g = grids[c];
+        g.kf = kf;
+        g.b0 = (int64_t)std::llround(q.f0 * kf * T) - kf;
+        g.nf = nf;
+        g.ns = ns;
+        g.fdot0 = q.fdot - 2.0 * o->dfdot;
+        g.dfdot = dfd;
+        g.t0 = o->t0;
+        if (g.b0 < 0) return fail(FH_E_INVALID, "candidate %d lies below the first fine bin", c);
+        prm[4 * c + 0] = (double)g.b0 / (kf * T);
+        prm[4 * c + 1] = 1.0 / (kf * T);
+        prm[4 * c + 2] = g.fdot0;
+        prm[4 * c + 3] = dfd;
+        // peaks whose stripes can reach the refined bins: Doppler and
+        // spin-down drift over the observation, plus one bin each side
+        const double f_lo = (double)g.b0 / (kf * T), f_hi = (double)(g.b0 + nf) / (kf * T);
+        const double fd_max = std::max(std::fabs(g.fdot0), std::fabs(g.fdot0 + (ns - 1) * dfd));
+        const int64_t margin = (int64_t)std::ceil((f_hi * pm->v_max * 1.01 + fd_max * tau) * T) + 2;
+        klo[c] = (int32_t)std::max<int64_t>(0, (int64_t)std::floor(f_lo * T) - margin);
+        khi[c] = (int32_t)std::min<int64_t>((int64_t)1 << 30, (int64_t)std::ceil(f_hi * T) + margin + 1);
+        width = std::max(width, khi[c] - klo[c]);
+        kmin = std::min(kmin, klo[c]);
+        kmax = std::max(kmax, khi[c] - 1);
+        for (int j = -L; j <= L; ++j)
+            for (int i = -L; i <= L; ++i) {
+                const int d = (j + L) * ks + (i + L);
+                double lam = q.lambda + i * (q.dlambda / ks), bet = q.beta + j * (q.dbeta / ks);
+                if (std::fabs(bet) > 0.5 * M_PI) {  // over a pole
+                    lam += M_PI;
+                    bet = (bet > 0 ? M_PI : -M_PI) - bet;
+                }
+                lam = std::fmod(lam, 2.0 * M_PI);
+                if (lam < 0) lam += 2.0 * M_PI;
+                lamb[2 * ((size_t)c * n_dir + d)] = lam;
+                lamb[2 * ((size_t)c * n_dir + d) + 1] = bet;
+                const double x = std::cos(bet) * std::cos(lam), ye = std::cos(bet) * std::sin(lam),
+                             ze = std::sin(bet);
+                double n[3] = {x, ye * ce - ze * se, ye * se + ze * ce};
+                const double r = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                for (int k = 0; k < 3; ++k) sky[3 * ((size_t)c * n_dir + d) + k] = n[k] / r;
+            }
+    }
+    // the sliced peakmap (context-owned arrays, reused by every candidate)
+    const int32_t N = pm->n_fft;
+    const int64_t cap = std::min<int64_t>((int64_t)N * width, pm->n_peaks);
+    if ((s = ctx->rf_offsets.ensure(8 * (size_t)(N + 1), st)) || (s = ctx->rf_bins.ensure(4 * (size_t)cap + 4, st)) ||
+        (s = ctx->rf_t.ensure(8 * (size_t)N, st)) || (s = ctx->rf_v.ensure(24 * (size_t)N, st)) ||
+        (s = ctx->rf_first.ensure(8 * (size_t)N, st)) || (s = ctx->rf_counts.ensure(4 * (size_t)N, st)) ||
+        (s = ctx->rf_cands.ensure(sizeof(fh_candidate) * 2 * (size_t)n_cand * n_dir, st)) ||
+        (s = ctx->rf_aux.ensure(8 * aux.size(), st)))
+        return s;
+    fh_peakmap sub(*pm);
+    sub.d_offsets = (int64_t *)ctx->rf_offsets.ptr;
+    sub.d_bins = (int32_t *)ctx->rf_bins.ptr;
+    sub.d_t = (double *)ctx->rf_t.ptr;
+    sub.d_v = (double *)ctx->rf_v.ptr;
+    sub.n_peaks = cap;
+    sub.k_min = kmin;
+    sub.k_max = kmax;
+    sub.max_per_fft = std::min<int32_t>(pm->max_per_fft, width);
+    for (int c = 0; c < n_cand; ++c)
+        if ((s = check_grid(&sub, &grids[c]))) return s;
+    HIP_OK(hipMemcpyAsync(sub.d_t, pm->d_t, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(sub.d_v, pm->d_v, 24 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    const bool weighted = d_w != nullptr;
+    const Plan p = make_plan(grids[0], choose_tile_bins(ctx, &sub, &grids[0], 0, weighted));
+    ChunkBufs b;
+    if ((s = ensure_workspace(ctx, &sub, &grids[0], p, n_dir, n_cand * n_dir, weighted, st, b))) return s;
+    if ((s = upload_sky(ctx, sky.data(), n_cand * n_dir, b, st))) return s;
+    // the auxiliary arrays go through the (now idle) pinned sky buffer
+    if ((s = ctx->cur->h_sky.ensure(8 * aux.size(), st))) return s;
+    HIP_OK(hipStreamSynchronize(st));
+    std::memcpy(ctx->cur->h_sky.ptr, aux.data(), 8 * aux.size());
+    HIP_OK(hipMemcpyAsync(ctx->rf_aux.ptr, ctx->cur->h_sky.ptr, 8 * aux.size(), hipMemcpyHostToDevice, st));
+    fh_select sel{nf, nf, -1, o->theta};
+    fh_candidate *dc = (fh_candidate *)ctx->rf_cands.ptr;
+    for (int c = 0; c < n_cand; ++c) {
+        HIP_OK(launch_slice(N, pm->d_offsets, pm->d_bins, klo[c], khi[c], (int64_t *)ctx->rf_first.ptr,
+                            (int32_t *)ctx->rf_counts.ptr, sub.d_offsets, sub.d_bins, st));
+        ChunkBufs bc = b;
+        bc.sky = b.sky + 3 * (int64_t)c * n_dir;
+        if ((s = run_search(ctx, &sub, &grids[c], p, n_dir, n_dir, d_w, 0, FH_SCHED_PERSISTENT, &sel,
+                            dc + 2 * (int64_t)c * n_dir, bc, st)))
+            return s;
+    }
+    const double *daux = (const double *)ctx->rf_aux.ptr;
+    HIP_OK(launch_refine_pick(n_cand, n_dir, dc, daux, daux + 4 * (size_t)n_cand, d_out, st));
+    return FH_OK;
+}
+
 
 fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int32_t tile_bins,
                         fh_plan_info *out) {
