@@ -57,7 +57,7 @@ struct TileArgs {
     int32_t kf, nf, ns, W;        // W: fine bins per tile
     int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
     int32_t n_slots;              // sky directions in this chunk
-    const int64_t *Y;             // [slot][P] stripe edges (2^-16 fine bins, see prep kernel)
+    const uint32_t *Y;            // [slot][P] low words of the stripe edges (2^-16 fine bins)
     const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] sorted windows
     const int64_t *dg;            // [N] row step of the stripe edge (2^-16 fine bins)
     const int32_t *rowt;          // [N][16] row terms -j dG_i mod 2^32, j < 16
@@ -83,18 +83,20 @@ hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
-                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st);
+                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, uint32_t *Y32,
+                       hipStream_t st);
 // fused stripe edges + weights + windows (LDS-staged edges of F FFTs per
 // workgroup); F = front_ffts_per_block(max peaks of one FFT), 0 when even one
 // FFT's edges do not fit (then use launch_prep + launch_windows)
 constexpr int kFrontLdsBytes = 48 * 1024;
+constexpr int kFrontMaxF = 16;
 int front_ffts_per_block(int32_t max_per_fft);
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                         const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                        const int64_t *g0, const int64_t *dg, int64_t *Y, const float *w,
+                        const int64_t *g0, const int64_t *dg, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
-                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int2 *win,
-                        hipStream_t st);
+                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
+                        int2 *win, hipStream_t st);
 // window rows sorted by window size per tile-wave run (see k_sort_windows)
 hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t n_slots, const int2 *win,
                                int2 *wsorted, hipStream_t st);

@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(256) k_prep(
     const int32_t *__restrict__ bins, const double *__restrict__ v,
     const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
     int64_t *__restrict__ Y, const float *__restrict__ w, int32_t w_stride,
-    const WeightStats *__restrict__ ws, int32_t ws_stride, uint32_t *__restrict__ wq) {
+    const WeightStats *__restrict__ ws, int32_t ws_stride, uint32_t *__restrict__ wq,
+    uint32_t *__restrict__ Y32) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int slot = blockIdx.y;
@@ -173,13 +174,19 @@ __global__ void __launch_bounds__(256) k_prep(
     // FFT i's edges start at offsets[i] + kYPad * i and are followed by kYPad
     // sentinels
     int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
+    uint32_t *Ys32 = Y32 + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
     const int64_t e = offsets[i + 1];
     for (int64_t p = offsets[i] + lane; p < e; p += 64) {
         double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
         x = x * kQd;
-        Ys[p] = (int64_t)floor(x) + c;
+        const int64_t y = (int64_t)floor(x) + c;
+        Ys[p] = y;
+        Ys32[p] = (uint32_t)y;
     }
-    if (lane < kYPad) Ys[e + lane] = kYSentinel;
+    if (lane < kYPad) {
+        Ys[e + lane] = kYSentinel;
+        Ys32[e + lane] = (uint32_t)kYSentinel;
+    }
     if (w != nullptr && lane == 0) {
         const WeightStats st = ws[(int64_t)slot * ws_stride];
         double wi = (double)w[(int64_t)slot * w_stride + i];
@@ -202,46 +209,59 @@ __global__ void __launch_bounds__(256) k_front(
     int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ bins, const double *__restrict__ v,
     const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
-    const int64_t *__restrict__ dg, int64_t *__restrict__ Y, const float *__restrict__ w,
+    const int64_t *__restrict__ dg, uint32_t *__restrict__ Y, const float *__restrict__ w,
     int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
     uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
     int2 *__restrict__ win) {
     extern __shared__ int64_t ys[];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    __shared__ int64_t s_off[kFrontMaxF + 1];  // offsets of the block's FFTs
+    __shared__ int64_t s_c[kFrontMaxF];        // per-FFT constant of the edge
+    __shared__ double s_r[kFrontMaxF];         // per-FFT inverse Doppler factor
     const int slot = blockIdx.y;
     const int f0 = blockIdx.x * F;
     const int fe = min(f0 + F, n_fft);
+    const int nfl = fe - f0;  // FFTs of this block (<= 0 for padding blocks)
     const int32_t n_pad = win_stride(n_fft);
-    int64_t *Yslot = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
+    uint32_t *Yslot = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     // padded index of the first staged edge
     const int64_t pb = f0 < n_fft ? offsets[f0] + (int64_t)kYPad * f0 : 0;
 
-    // stripe edges (as k_prep) and weights, one wave per FFT
+    // per-FFT terms (r, constant, weight), one thread per FFT
     const double *n = sky + 3 * (int64_t)slot;
-    for (int i = f0 + wave; i < fe; i += 4) {
+    if ((int)threadIdx.x <= nfl) s_off[threadIdx.x] = offsets[f0 + threadIdx.x];
+    if ((int)threadIdx.x < nfl) {
+        const int i = f0 + threadIdx.x;
         const double *vi = v + 3 * (int64_t)i;
         double d = vi[0] * n[0];
         d = d + vi[1] * n[1];
         d = d + vi[2] * n[2];
         d = 1.0 + d;
-        const double r = 1.0 / d;
-        const int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
-        int64_t *Ys = Yslot + (int64_t)kYPad * i;
-        const int64_t st = (int64_t)kYPad * i - pb;
-        const int64_t e = offsets[i + 1];
-        for (int64_t p = offsets[i] + lane; p < e; p += 64) {
-            double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
-            x = x * kQd;
-            const int64_t y = (int64_t)floor(x) + c;
-            Ys[p] = y;
-            ys[p + st] = y;
-        }
-        if (lane < kYPad) Ys[e + lane] = kYSentinel;
-        if (w != nullptr && lane == 0) {
+        s_r[threadIdx.x] = 1.0 / d;
+        s_c[threadIdx.x] = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+        if (w != nullptr) {
             const WeightStats wst = ws[(int64_t)slot * ws_stride];
             double wi = (double)w[(int64_t)slot * w_stride + i];
             wq[(int64_t)slot * n_fft + i] = wst.bad ? 0u : (uint32_t)rint(ldexp(wi, wst.frac_bits));
+        }
+    }
+    __syncthreads();
+
+    // stripe edges (as k_prep) of all the block's peaks, spread over every
+    // thread; the FFT of a peak advances monotonically per thread
+    if (nfl > 0) {
+        const int64_t P0 = s_off[0], P1 = s_off[nfl];
+        int l = 0;
+        for (int64_t p = P0 + threadIdx.x; p < P1; p += blockDim.x) {
+            while (s_off[l + 1] <= p) ++l;
+            double x = (double)((int64_t)kf * (int64_t)bins[p]) * s_r[l];
+            x = x * kQd;
+            const int64_t y = (int64_t)floor(x) + s_c[l];
+            Yslot[p + (int64_t)kYPad * (f0 + l)] = (uint32_t)y;  // the tiles use the low word
+            ys[p - P0 + (int64_t)kYPad * l] = y;
+        }
+        for (int t = threadIdx.x; t < nfl * kYPad; t += blockDim.x) {
+            const int fl = t / kYPad;
+            Yslot[s_off[fl + 1] + (int64_t)kYPad * (f0 + fl) + (t - fl * kYPad)] = (uint32_t)kYSentinel;
         }
     }
     __syncthreads();
@@ -542,185 +562,11 @@ struct Quad {
     int cmax;            // largest window of the four groups
 };
 
-template <bool WEIGHTED, bool MAP, bool COLMAX>
-__device__ __forceinline__ void tile_body(const TileArgs &A, int slot, int rb, int jb,
-                                          uint32_t *__restrict__ lds) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nwave = blockDim.x >> 6;
-    const int j = lane & 15;
-    const int grp = lane >> 4;
-    const int W = A.W, kf = A.kf;
-    const int wc = W + kf - 1;
-    // LDS column c holds fine bin c0 + c, c in [0, wc); columns wc + g are
-    // the dumps of the four lane groups.
-    const int nwords = kTileRows * (wc + kDumpCols);
-
-    for (int x = tid * 4; x < nwords; x += blockDim.x * 4) {
-        if (x + 3 < nwords) {
-            *reinterpret_cast<uint4 *>(lds + x) = make_uint4(0, 0, 0, 0);
-        } else {
-            for (int y = x; y < nwords; ++y) lds[y] = 0;
-        }
-    }
-    lds_barrier();
-
-    const int s0 = rb * kTileRows;
-    const int32_t c0 = jb * W - (kf - 1);
-    const int g = rb / kRowBlocksPerGroup;
-    const int32_t n_pad = win_stride(A.n_fft);
-    const int2 *__restrict__ win = A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * n_pad;
-    // low 32 bits of the stripe edges (all the tile needs: see stripe_step)
-    const uint32_t *__restrict__ Ylo =
-        reinterpret_cast<const uint32_t *>(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
-    const uint32_t *__restrict__ wq = WEIGHTED ? A.wq + (int64_t)slot * A.n_fft : nullptr;
-    const uint32_t dump = (uint32_t)(wc + grp);
-    const uint32_t lane_off = (uint32_t)j;
-    const uint32_t c0q = (uint32_t)c0 << kFrac;
-    const uint32_t below = (1u << j) - 1u;           // pattern lanes below j
-    const uint32_t mtab = chunk_pattern(lane);       // lane n holds m(n), n <= 16
-
-    // Each wave takes a run of wave_ffts(N) FFTs, four at a time (one per
-    // lane group; windows past the last FFT are empty).  A block's window
-    // data are loaded two blocks ahead and its stripe edges one block ahead
-    // (a ring of three blocks), so that the accumulation of a block never
-    // waits for memory.  Every load is issued on every path so that the wait
-    // counts stay exact.
-    const int per = wave_ffts(A.n_fft);
-    const int i_begin = wave * per;
-    const int nblk = per >> 2;
-    const int i_last = A.n_fft - 1;
-
-    // window data of block bb (stage 1).  The ring prefetches two blocks past
-    // the wave's last one (never consumed); those reads stay inside the
-    // window row.
-    const __amdgpu_buffer_rsrc_t r_win = buf(win), r_y = buf(Ylo), r_t = buf(A.rowt), r_dg = buf(A.dg);
-    const __amdgpu_buffer_rsrc_t r_wq = buf(WEIGHTED ? (const void *)wq : (const void *)A.dg);
-    auto stage_w = [&](Quad &Q, int bb) {
-        const uint32_t e = (uint32_t)(i_begin + 4 * bb + grp);
-        const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(r_win, min(e, (uint32_t)(n_pad - 1)) * 8u, 0, 0);
-        Q.lo = (int)w2[0];
-        Q.pk = (int)w2[1];
-    };
-    // stripe edges, row terms and weights of block bb (stage 2): the chunk
-    // sizes follow the largest window of the four groups, group 0's (the runs
-    // are sorted by window size)
-    auto stage_y = [&](Quad &Q) {
-        Q.cnt = Q.pk & 0xFFFF;
-        const uint32_t fc = min((uint32_t)(i_begin + (Q.pk >> 16)), (uint32_t)i_last);
-        Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
-        Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
-        Q.wq = WEIGHTED ? ld_u32(r_wq, fc * 4u) : 1u;
-        Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
-        const int n1 = min(Q.cmax, 16);
-        const int n2 = min(max(Q.cmax - 16, 0), 16);
-        Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
-        Q.m2 = __builtin_amdgcn_readlane(mtab, n2);
-        Q.q1 = (int32_t)__builtin_popcount(Q.m1 & below);
-        Q.q2 = 16 + (int32_t)__builtin_popcount(Q.m2 & below);
-        Q.y0 = ld_u32(r_y, (uint32_t)(Q.lo + Q.q1) * 8u);
-        Q.y1 = ld_u32(r_y, (uint32_t)(Q.lo + Q.q2) * 8u);
-    };
-    auto consume = [&](const Quad &Q) {
-        const uint32_t base = c0q + (uint32_t)__mul24(s0, Q.dg);  // |dG| < 2^23
-        uint32_t val = Q.wq;
-        asm volatile("" : "+v"(val));
-        const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
-        stripe_chunk(Q.m1, v0, Q.t, dump, lane_off, val, lds);
-        if (Q.cmax > 16) {
-            const uint32_t v1 = Q.q2 < Q.cnt ? Q.y1 - base : kFarEdge;
-            stripe_chunk(Q.m2, v1, Q.t, dump, lane_off, val, lds);
-        }
-        // windows longer than 32 peaks: further chunks, loaded here
-        for (int off = 32; off < Q.cmax; off += 16) {
-            const uint32_t m = __builtin_amdgcn_readlane(mtab, min(Q.cmax - off, 16));
-            const int32_t q = off + (int32_t)__builtin_popcount(m & below);
-            uint32_t v = kFarEdge;
-            if (q < Q.cnt) v = ld_u32(r_y, (uint32_t)(Q.lo + q) * 8u) - base;
-            stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
-        }
-    };
-
-    if (nblk > 0) {
-        Quad qa, qb, qc;
-        stage_w(qa, 0);
-        stage_w(qb, 1);
-        stage_y(qa);
-        for (int b = 0; b < nblk; b += 3) {
-            stage_w(qc, b + 2);
-            stage_y(qb);
-            consume(qa);
-            stage_w(qa, b + 3);
-            stage_y(qc);
-            consume(qb);
-            stage_w(qb, b + 4);
-            stage_y(qa);
-            consume(qc);
-        }
-    }
-    lds_barrier();
-
-    // Row sums: H(x) = sum_{c = x}^{x + K_f - 1} P(c), x in [0, W): the +w at
-    // the stripe start and the -w K_f bins later, prefix-summed along the row.
-    const int nseg = blockDim.x / kTileRows;
-    const int seg = tid >> 4;
-    const int len = (W + nseg - 1) / nseg;
-    const int x0 = seg * len;
-    int x1 = x0 + len < W ? x0 + len : W;
-    const int64_t bbase = (int64_t)jb * W;
-    if (bbase + x1 > A.nf) x1 = (int)(A.nf - bbase);
-    const int s = s0 + j;
-    const bool row_ok = s < A.ns;
-    const uint32_t *__restrict__ P = lds + j;
-    float scale = 1.0f;
-    if (WEIGHTED) scale = ldexpf(1.0f, -A.ws[(int64_t)slot * A.ws_stride].frac_bits);
-    uint32_t acc = 0;
-    if (x0 < x1)
-        for (int c = x0; c < x0 + kf - 1; ++c) acc += P[c * kTileRows];
-    for (int x = x0; x < x1; ++x) {
-        acc += P[(x + kf - 1) * kTileRows];
-        const int64_t b = bbase + x;
-        if (MAP && row_ok) {
-            if (WEIGHTED) A.map_f32[(int64_t)s * A.nf + b] = (float)acc * scale;
-            else A.map_i32[(int64_t)s * A.nf + b] = (int32_t)acc;
-        }
-        if (COLMAX) {
-            // largest value over the 16 rows (DPP row_shr prefix max: lane 15
-            // ends with it), then the smallest row holding it (prefix min)
-            const uint32_t a = row_ok ? acc : 0u;
-            uint32_t mx = a;
-            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x111, 0xF, 0xF, false));
-            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x112, 0xF, 0xF, false));
-            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x114, 0xF, 0xF, false));
-            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x118, 0xF, 0xF, false));
-            const uint32_t top = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x15F, 0xF, 0xF, true);
-            int r = row_ok && a == top ? j : kTileRows;
-            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x111, 0xF, 0xF, false));
-            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x112, 0xF, 0xF, false));
-            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x114, 0xF, 0xF, false));
-            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x118, 0xF, 0xF, false));
-            if (j == kTileRows - 1)
-                atomicMax(A.colmax + (int64_t)slot * A.nf + b,
-                          ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s0 + r)));
-        }
-        acc -= P[x * kTileRows];
-    }
-}
-
 __device__ __forceinline__ void decode_tile(const TileArgs &A, int t, int &slot, int &rb, int &jb) {
     jb = t % A.nbb;
     const int r = t / A.nbb;
     rb = r % A.nrb;
     slot = r / A.nrb;
-}
-
-template <bool WEIGHTED, bool MAP, bool COLMAX>
-__global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
-    extern __shared__ uint32_t lds[];
-    int slot, rb, jb;
-    decode_tile(A, A.tile_base + blockIdx.x, slot, rb, jb);
-    tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
 }
 
 // Persistent form.  Tile groups (sky, bin block) are dealt round-robin to
@@ -755,6 +601,264 @@ __device__ int steal_tile(const TileArgs &A, int home) {
     return -1;
 }
 
+// LDS words of a tile: W + K_f - 1 columns plus the dump columns, 16 rows.
+__device__ __forceinline__ int tile_words(const TileArgs &A) {
+    return kTileRows * (A.W + A.kf - 1 + kDumpCols);
+}
+
+__device__ __forceinline__ void tile_zero(const TileArgs &A, uint32_t *__restrict__ lds) {
+    const int nwords = tile_words(A);
+    for (int x = threadIdx.x * 4; x < nwords; x += blockDim.x * 4) {
+        if (x + 3 < nwords) {
+            *reinterpret_cast<uint4 *>(lds + x) = make_uint4(0, 0, 0, 0);
+        } else {
+            for (int y = x; y < nwords; ++y) lds[y] = 0;
+        }
+    }
+}
+
+// Output phase of tile (slot, rb, jb): per-row window sums of the start
+// histogram, written as a map and/or reduced to per-bin column maxima.
+// Column maxima: a lane group owns a segment [x0, x1) of columns.  Its first
+// K_f - 1 columns are still read by the previous group's window sums, so
+// their maxima are reduced across the group's 16 lanes at once (DPP); every
+// later column is read by its own group only, and its window sums replace
+// its start counts in place.  After a barrier one thread per such column
+// reduces the 16 rows in registers and updates the global maximum.
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__device__ __forceinline__ void tile_output(const TileArgs &A, int slot, int rb, int jb,
+                                            uint32_t *__restrict__ lds) {
+    const int tid = threadIdx.x;
+    const int j = tid & 15;
+    const int W = A.W, kf = A.kf;
+    const int s0 = rb * kTileRows;
+    // Row sums: H(x) = sum_{c = x}^{x + K_f - 1} P(c), x in [0, W): the +w at
+    // the stripe start and the -w K_f bins later, prefix-summed along the row.
+    const int nseg = blockDim.x / kTileRows;
+    const int seg = tid >> 4;
+    const int len = (W + nseg - 1) / nseg;
+    const int64_t bbase = (int64_t)jb * W;
+    const int xend = (int)min((int64_t)W, (int64_t)A.nf - bbase);  // columns of the map
+    const int x0 = seg * len;
+    const int x1 = min(x0 + len, xend);
+    const int xs = x0 + kf - 1;  // first column rewritten in place
+    const int s = s0 + j;
+    const bool row_ok = s < A.ns;
+    uint32_t *__restrict__ P = lds + j;
+    unsigned long long *__restrict__ cm = A.colmax + (int64_t)slot * A.nf + bbase;
+    float scale = 1.0f;
+    if (WEIGHTED) scale = ldexpf(1.0f, -A.ws[(int64_t)slot * A.ws_stride].frac_bits);
+    uint32_t acc = 0;
+    if (x0 < x1)
+        for (int c = x0; c < x0 + kf - 1; ++c) acc += P[c * kTileRows];
+    for (int x = x0; x < x1; ++x) {
+        acc += P[(x + kf - 1) * kTileRows];
+        const int64_t b = bbase + x;
+        if (MAP && row_ok) {
+            if (WEIGHTED) A.map_f32[(int64_t)s * A.nf + b] = (float)acc * scale;
+            else A.map_i32[(int64_t)s * A.nf + b] = (int32_t)acc;
+        }
+        const uint32_t trail = P[x * kTileRows];
+        if (COLMAX && x < xs) {
+            // largest value over the 16 rows (DPP row_shr prefix max: lane 15
+            // ends with it), then the smallest row holding it (prefix min)
+            const uint32_t a = row_ok ? acc : 0u;
+            uint32_t mx = a;
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x111, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x112, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x114, 0xF, 0xF, false));
+            mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x118, 0xF, 0xF, false));
+            const uint32_t top = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x15F, 0xF, 0xF, true);
+            int r = row_ok && a == top ? j : kTileRows;
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x111, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x112, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x114, 0xF, 0xF, false));
+            r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x118, 0xF, 0xF, false));
+            if (j == kTileRows - 1)
+                atomicMax(cm + x, ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s0 + r)));
+        } else if (COLMAX) {
+            P[x * kTileRows] = row_ok ? acc : 0u;
+        }
+        acc -= trail;
+    }
+    if (!COLMAX) return;
+    lds_barrier();
+    // columns rewritten in place: x in [x0 + K_f - 1, x1) of each segment
+    for (int x = tid; x < xend; x += blockDim.x) {
+        const int sx = x / len;
+        if (x < sx * len + kf - 1) continue;
+        const uint4 *q = reinterpret_cast<const uint4 *>(lds + x * kTileRows);
+        const uint4 h0 = q[0], h1 = q[1], h2 = q[2], h3 = q[3];
+        const uint32_t h[16] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w,
+                                h2.x, h2.y, h2.z, h2.w, h3.x, h3.y, h3.z, h3.w};
+        uint32_t top = h[0];
+#pragma unroll
+        for (int k = 1; k < kTileRows; ++k) top = max(top, h[k]);
+        // smallest row holding the maximum (rows past the grid hold 0, and
+        // row 0 always exists, so a row past the grid is never chosen)
+        int r = kTileRows - 1;
+#pragma unroll
+        for (int k = kTileRows - 2; k >= 0; --k) r = h[k] == top ? k : r;
+        atomicMax(cm + x, ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s0 + r)));
+    }
+}
+
+// The tiles of one workgroup.  Each wave takes a run of wave_ffts(N) FFTs,
+// four at a time (one per lane group; windows past the last FFT are empty).
+// A block's window data are loaded two blocks ahead and its stripe edges one
+// block ahead (a ring of three blocks), so that the accumulation of a block
+// never waits for memory; the first two blocks of the next tile are loaded
+// during the output phase of the current one.  Every load is issued on every
+// path so that the wait counts stay exact.  PERSISTENT: tiles come from the
+// XCD queues until all are exhausted; otherwise the workgroup runs tile
+// tile_base + blockIdx.x only.
+template <bool WEIGHTED, bool MAP, bool COLMAX, bool PERSISTENT>
+__device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restrict__ lds, int *s_next) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = lane & 15;
+    const int grp = lane >> 4;
+    const int W = A.W, kf = A.kf;
+    const int wc = W + kf - 1;
+    // LDS column c holds fine bin c0 + c, c in [0, wc); columns wc + g are
+    // the dumps of the four lane groups.
+    const uint32_t dump = (uint32_t)(wc + grp);
+    const uint32_t lane_off = (uint32_t)j;
+    const uint32_t below = (1u << j) - 1u;           // pattern lanes below j
+    const uint32_t mtab = chunk_pattern(lane);       // lane n holds m(n), n <= 16
+    const int32_t n_pad = win_stride(A.n_fft);
+    const int per = wave_ffts(A.n_fft);
+    const int i_begin = wave * per;
+    const int nblk = per >> 2;
+    const int i_last = A.n_fft - 1;
+    const int home = blockIdx.x % kXcds;
+    const __amdgpu_buffer_rsrc_t r_t = buf(A.rowt), r_dg = buf(A.dg);
+
+    // per-tile buffers: window row, stripe edges and weights of the slot
+    struct Bufs {
+        __amdgpu_buffer_rsrc_t win, y, wq;
+    };
+    auto tile_bufs = [&](int t) {
+        int slot, rb, jb;
+        decode_tile(A, t, slot, rb, jb);
+        const int g = rb / kRowBlocksPerGroup;
+        Bufs b;
+        b.win = buf(A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * n_pad);
+        // low 32 bits of the stripe edges (all the tile needs: see stripe_word)
+        b.y = buf(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
+        b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.dg);
+        return b;
+    };
+    // window data of block bb (stage 1).  The ring prefetches two blocks past
+    // the wave's last one (never consumed); those reads stay inside the
+    // window row.
+    auto stage_w = [&](Quad &Q, int bb, const Bufs &B) {
+        const uint32_t e = (uint32_t)(i_begin + 4 * bb + grp);
+        const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(B.win, min(e, (uint32_t)(n_pad - 1)) * 8u, 0, 0);
+        Q.lo = (int)w2[0];
+        Q.pk = (int)w2[1];
+    };
+    // stripe edges, row terms and weights of block bb (stage 2): the chunk
+    // sizes follow the largest window of the four groups, group 0's (the runs
+    // are sorted by window size)
+    auto stage_y = [&](Quad &Q, const Bufs &B) {
+        Q.cnt = Q.pk & 0xFFFF;
+        const uint32_t fc = min((uint32_t)(i_begin + (Q.pk >> 16)), (uint32_t)i_last);
+        Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
+        Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
+        Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
+        Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
+        const int n1 = min(Q.cmax, 16);
+        const int n2 = min(max(Q.cmax - 16, 0), 16);
+        Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
+        Q.m2 = __builtin_amdgcn_readlane(mtab, n2);
+        Q.q1 = (int32_t)__builtin_popcount(Q.m1 & below);
+        Q.q2 = 16 + (int32_t)__builtin_popcount(Q.m2 & below);
+        Q.y0 = ld_u32(B.y, (uint32_t)(Q.lo + Q.q1) * 4u);
+        Q.y1 = ld_u32(B.y, (uint32_t)(Q.lo + Q.q2) * 4u);
+    };
+
+    int t;
+    if (PERSISTENT) {
+        if (tid == 0) s_next[0] = steal_tile(A, home);
+    }
+    tile_zero(A, lds);
+    lds_barrier();
+    t = PERSISTENT ? s_next[0] : A.tile_base + (int)blockIdx.x;
+    if (t < 0 || nblk == 0) return;  // nblk > 0 whenever there is an FFT
+    Quad qa, qb, qc;
+    Bufs cur = tile_bufs(t);
+    stage_w(qa, 0, cur);
+    stage_w(qb, 1, cur);
+    stage_y(qa, cur);
+    for (int it = 0;; ++it) {
+        int pos = 0;
+        if (PERSISTENT && tid == 0) pos = atomicAdd(A.queue_ctr + home, 1);
+        int slot, rb, jb;
+        decode_tile(A, t, slot, rb, jb);
+        const int s0 = rb * kTileRows;
+        const uint32_t c0q = (uint32_t)(jb * W - (kf - 1)) << kFrac;
+        auto consume = [&](const Quad &Q) {
+            const uint32_t base = c0q + (uint32_t)__mul24(s0, Q.dg);  // |dG| < 2^23
+            uint32_t val = Q.wq;
+            asm volatile("" : "+v"(val));
+            const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
+            stripe_chunk(Q.m1, v0, Q.t, dump, lane_off, val, lds);
+            if (Q.cmax > 16) {
+                const uint32_t v1 = Q.q2 < Q.cnt ? Q.y1 - base : kFarEdge;
+                stripe_chunk(Q.m2, v1, Q.t, dump, lane_off, val, lds);
+            }
+            // windows longer than 32 peaks: further chunks, loaded here
+            for (int off = 32; off < Q.cmax; off += 16) {
+                const uint32_t m = __builtin_amdgcn_readlane(mtab, min(Q.cmax - off, 16));
+                const int32_t q = off + (int32_t)__builtin_popcount(m & below);
+                uint32_t v = kFarEdge;
+                if (q < Q.cnt) v = ld_u32(cur.y, (uint32_t)(Q.lo + q) * 4u) - base;
+                stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
+            }
+        };
+        for (int b = 0; b < nblk; b += 3) {
+            stage_w(qc, b + 2, cur);
+            stage_y(qb, cur);
+            consume(qa);
+            stage_w(qa, b + 3, cur);
+            stage_y(qc, cur);
+            consume(qb);
+            stage_w(qb, b + 4, cur);
+            stage_y(qa, cur);
+            consume(qc);
+        }
+        int tn = -1;
+        if (PERSISTENT) {
+            if (tid == 0)
+                s_next[(it + 1) & 1] = pos < queue_len(A, home) ? queue_tile(A, home, pos) : steal_tile(A, home);
+        }
+        lds_barrier();
+        if (PERSISTENT) tn = s_next[(it + 1) & 1];
+        Bufs nxt = cur;
+        if (tn >= 0) {
+            nxt = tile_bufs(tn);
+            stage_w(qa, 0, nxt);
+            stage_w(qb, 1, nxt);
+        }
+        tile_output<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        if (tn < 0) break;
+        stage_y(qa, nxt);
+        lds_barrier();
+        tile_zero(A, lds);
+        lds_barrier();
+        cur = nxt;
+        t = tn;
+    }
+}
+
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
+    extern __shared__ uint32_t lds[];
+    run_tiles<WEIGHTED, MAP, COLMAX, false>(A, lds, nullptr);
+}
+
 // One workgroup per CU.  The next tile of the home queue is claimed when a
 // tile starts (its counter update overlaps the tile's work) and used when it
 // ends; an exhausted home queue sends the workgroup to the others.  Every
@@ -763,21 +867,7 @@ template <bool WEIGHTED, bool MAP, bool COLMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ int s_next[2];
-    const int home = blockIdx.x % kXcds;
-    if (threadIdx.x == 0) s_next[0] = steal_tile(A, home);
-    lds_barrier();
-    int t = s_next[0];
-    for (int it = 0; t >= 0; ++it) {
-        int pos = 0;
-        if (threadIdx.x == 0) pos = atomicAdd(A.queue_ctr + home, 1);
-        int slot, rb, jb;
-        decode_tile(A, t, slot, rb, jb);
-        tile_body<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
-        if (threadIdx.x == 0)
-            s_next[(it + 1) & 1] = pos < queue_len(A, home) ? queue_tile(A, home, pos) : steal_tile(A, home);
-        lds_barrier();
-        t = s_next[(it + 1) & 1];
-    }
+    run_tiles<WEIGHTED, MAP, COLMAX, true>(A, lds, s_next);
 }
 
 // ----------------------------------------------------------------------------
@@ -1032,28 +1122,31 @@ hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
-                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, hipStream_t st) {
+                       const WeightStats *ws, int32_t ws_stride, uint32_t *wq, uint32_t *Y32,
+                       hipStream_t st) {
     dim3 grid((n_fft + 3) / 4, n_slots);
     k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, Y, w, w_stride,
-                                 ws, ws_stride, wq);
+                                 ws, ws_stride, wq, Y32);
     return hipGetLastError();
 }
 
 int front_ffts_per_block(int32_t max_per_fft) {
-    for (int F = 16; F >= 1; F >>= 1)
+    for (int F = kFrontMaxF; F >= 1; F >>= 1)
         if ((int64_t)F * (max_per_fft + kYPad) * 8 <= kFrontLdsBytes) return F;
     return 0;
 }
 
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                         const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                        const int64_t *g0, const int64_t *dg, int64_t *Y, const float *w,
+                        const int64_t *g0, const int64_t *dg, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
-                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int2 *win,
-                        hipStream_t st) {
+                        int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
+                        int2 *win, hipStream_t st) {
     if (F < 1 || win_stride(n_fft) % F != 0) return hipErrorInvalidValue;
     dim3 grid(win_stride(n_fft) / F, n_slots);
-    k_front<<<grid, 256, kFrontLdsBytes, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
+    const size_t lds = ((size_t)F * (max_per_fft + kYPad) * 8 + 255) / 256 * 256;
+    if (F > kFrontMaxF || lds > (size_t)kFrontLdsBytes) return hipErrorInvalidValue;
+    k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
                                                w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win);
     return hipGetLastError();
 }

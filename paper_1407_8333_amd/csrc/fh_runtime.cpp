@@ -117,16 +117,16 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, rowt, Y, win, wsort, colmax, wq, ws, sky, qctr;
+    DevBuf g0, dg, rowt, Y, Y64, win, wsort, colmax, wq, ws, sky, qctr;
     PinnedBuf h_sky;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             b->release();
         h_sky.release();
     }
@@ -279,7 +279,9 @@ struct Timed {
 };
 
 struct ChunkBufs {
-    int64_t *g0, *dg, *Y;
+    int64_t *g0, *dg;
+    uint32_t *Y;   // low words of the stripe edges (what the tiles read)
+    int64_t *Y64;  // full stripe edges, only for the unfused window methods
     int32_t *rowt;
     int2 *win, *wsort;
     unsigned long long *colmax;
@@ -289,6 +291,17 @@ struct ChunkBufs {
     int32_t *qctr, *err;
 };
 
+// the unfused window methods (chosen, or forced when one FFT's edges do not
+// fit the fused front's LDS) search the full 64-bit edges in device memory
+bool needs_full_edges(const fh_ctx *ctx, const fh_peakmap *pm) {
+    return !(ctx->window_method == 2 && front_ffts_per_block(pm->max_per_fft) > 0);
+}
+
+// device bytes of the stripe edges of one direction
+int64_t edge_bytes_per_sky(const fh_ctx *ctx, const fh_peakmap *pm) {
+    return (needs_full_edges(ctx, pm) ? 12 : 4) * y_stride(pm->n_peaks, pm->n_fft);
+}
+
 fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
                            int slots, int n_sky, bool weighted, hipStream_t st, ChunkBufs &b) {
     const int64_t N = pm->n_fft;
@@ -296,7 +309,10 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
     if ((s = ctx->cur->rowt.ensure((size_t)4 * kTileRows * N, st))) return s;
-    if ((s = ctx->cur->Y.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
+    if ((s = ctx->cur->Y.ensure((size_t)4 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
+    if (needs_full_edges(ctx, pm) &&
+        (s = ctx->cur->Y64.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st)))
+        return s;
     if ((s = ctx->cur->win.ensure((size_t)8 * slots * p.nrbg * p.nbb * win_stride(N), st))) return s;
     if ((s = ctx->cur->wsort.ensure((size_t)8 * slots * p.nrbg * p.nbb * win_stride(N), st))) return s;
     if ((s = ctx->cur->colmax.ensure((size_t)8 * slots * g->nf, st))) return s;
@@ -308,7 +324,8 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     b.g0 = (int64_t *)ctx->cur->g0.ptr;
     b.dg = (int64_t *)ctx->cur->dg.ptr;
     b.rowt = (int32_t *)ctx->cur->rowt.ptr;
-    b.Y = (int64_t *)ctx->cur->Y.ptr;
+    b.Y = (uint32_t *)ctx->cur->Y.ptr;
+    b.Y64 = (int64_t *)ctx->cur->Y64.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
     b.wsort = (int2 *)ctx->cur->wsort.ptr;
     b.colmax = (unsigned long long *)ctx->cur->colmax.ptr;
@@ -372,13 +389,13 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     if (F > 0) {
         HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
                             g->b0, b.g0, b.dg, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
-                            p.nrbg, p.nbb, p.W, F, b.win, st));
+                            p.nrbg, p.nbb, p.W, F, pm->max_per_fft, b.win, st));
         HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
         return FH_OK;
     }
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
-                       g->kf, g->b0, b.g0, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, st));
-    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
+                       g->kf, g->b0, b.g0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, st));
+    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
     HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
     return FH_OK;
@@ -412,9 +429,9 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
 
 // chunk: as many directions as a bounded workspace holds (fewer launches,
 // more tiles per persistent launch)
-int default_chunk(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
+int default_chunk(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
     if (requested > 0) return requested;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
+    const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
     const int64_t by_mem = std::max<int64_t>(1, ((int64_t)16 << 30) / std::max<int64_t>(1, per_sky));
     return (int)std::min<int64_t>(by_mem, 256);
 }
@@ -940,7 +957,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->tile_bins = p.W;
     out->n_row_blocks = p.nrb;
     out->n_bin_blocks = p.nbb;
-    out->workspace_bytes = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
+    out->workspace_bytes = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
@@ -983,7 +1000,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
     if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g, weighted)) == ctx->tuned.end())
         if ((s = autotune(ctx, pm, g, n_sky, sky, d_w, w_stride, st))) return s;
     const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins, weighted));
-    int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(pm, g, p, o.sky_chunk);
+    int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(ctx, pm, g, p, o.sky_chunk);
     chunk = std::min(chunk, n_sky);
     ChunkBufs b;
     if ((s = ensure_workspace(ctx, pm, g, p, chunk, n_sky, weighted, st, b))) return s;
@@ -1005,7 +1022,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.wsort, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
         (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt,
-        (uint64_t)(uintptr_t)b.qctr};
+        (uint64_t)(uintptr_t)b.qctr, (uint64_t)(uintptr_t)b.Y64, (uint64_t)ctx->window_method};
     fh_ctx::GraphEntry *ge = nullptr;
     for (auto &e : ctx->graphs)
         if (e.key == key) ge = &e;
@@ -1110,9 +1127,10 @@ struct Lane {
 };
 
 // Workspace bytes of one search of `chunk` directions with plan p.
-int64_t search_footprint(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk, int n_sky) {
+int64_t search_footprint(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
+                         int n_sky) {
     const int64_t N = pm->n_fft;
-    const int64_t per_sky = 8 * y_stride(pm->n_peaks, pm->n_fft) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
+    const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
                             8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
     return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
 }
@@ -1245,9 +1263,9 @@ fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id) 
     // the largest chunk whose footprint fits one lane's share of the budget
     const int64_t share = srv->budget / (int64_t)srv->lanes.size();
     int chunk = std::min<int>(req->n_sky, 256);
-    while (chunk > 1 && search_footprint(req->pm, &req->grid, p, chunk, req->n_sky) > share) chunk = (chunk + 1) / 2;
+    while (chunk > 1 && search_footprint(ctx, req->pm, &req->grid, p, chunk, req->n_sky) > share) chunk = (chunk + 1) / 2;
     R.chunk = chunk;
-    R.footprint = search_footprint(req->pm, &req->grid, p, chunk, req->n_sky);
+    R.footprint = search_footprint(ctx, req->pm, &req->grid, p, chunk, req->n_sky);
     if (R.footprint > srv->budget) {
         srv->next_id--;
         return fail(FH_E_UNSUPPORTED, "request needs %lld workspace bytes, over the %lld-byte budget",
