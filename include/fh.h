@@ -288,6 +288,64 @@ typedef struct fh_refined {
 fh_status fh_refine(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_cand, const fh_coarse_cand *cands,
                     const fh_refine_opts *opts, const float *d_w, fh_refined *d_out, void *stream);
 
+/* ---- peakmap cleaning ------------------------------------------------------
+ * Sec. "Removal of time and frequency domain disturbances".  Every function
+ * here runs on `stream`; those returning a new peakmap wait for it (the
+ * surviving peak count sizes the result), and the new handle is owned by the
+ * caller (fh_peakmap_release).  FH_E_INVALID for bad arguments. */
+
+/* Cells of the gross histogram (subsection on spectral wandering lines).
+ * FFT i lies in time cell floor((t_i - t_origin) / dt_h) and a peak of
+ * natural bin k in frequency cell floor(k / (df_h T_FFT)) - c0 (FP64: one
+ * product df_h T_FFT, one division and a floor each); the histogram holds
+ * the cells [0, n_t) x [0, n_f).  dt_h, df_h > 0, n_t, n_f >= 1. */
+typedef struct fh_gross {
+    double t_origin, dt_h, df_h;
+    int64_t c0;
+    int32_t n_t, n_f;
+} fh_gross;
+
+/* d_hist: device int32 [n_t][n_f] (row-major), overwritten with the number
+ * of peaks in each cell; peaks outside the cells are not counted. */
+fh_status fh_gross_histogram(fh_ctx *ctx, const fh_peakmap *pm, const fh_gross *geo, int32_t *d_hist,
+                             void *stream);
+
+/* Wandering-line veto: a new peakmap without the peaks whose cell holds more
+ * than `threshold` peaks (the paper takes E_H + 2-3 sigma_H); peaks outside
+ * the cells are kept.  d_hist (device int32 [n_t][n_f], caller-owned) holds
+ * the gross histogram on return. */
+fh_status fh_clean_gross(fh_ctx *ctx, const fh_peakmap *pm, const fh_gross *geo, double threshold,
+                         int32_t *d_hist, void *stream, fh_peakmap **out);
+
+/* Persistency (subsection on lines of constant frequency): d_counts (device
+ * int32 [k_hi - k_lo]) = number of peaks at each natural bin k in
+ * [k_lo, k_hi), i.e. of FFTs holding a peak there. */
+fh_status fh_bin_counts(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi, int32_t *d_counts,
+                        void *stream);
+
+/* Robust statistic (appendix "Robust statistic"): out[0] = m1 = median of
+ * d_x[0 .. n), out[1] = m2 = median(|x - m1|) / 0.6745, a median of an even
+ * count being the mean of the two middle values.  Exact (integer ranks).
+ * Requires n >= 1 and 0 <= x <= x_max (checked on the device: FH_E_INVALID).
+ * out: host array; waits for `stream`. */
+fh_status fh_robust_stats(fh_ctx *ctx, const int32_t *d_x, int32_t n, int32_t x_max, double out[2],
+                          void *stream);
+
+/* Lines of constant frequency without Doppler correction (the third option
+ * of that subsection): per fine bin of `g`, the largest count over the grid's
+ * spin-down rows of the unweighted Hough map of pm computed with v . n = 0
+ * (rows around zero spin-down admit a slowly drifting line).  d_out: device
+ * int32 [g->nf]. */
+fh_status fh_line_counts(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int32_t *d_out, void *stream);
+
+/* Veto of natural bins: a new peakmap without the peaks of natural bin k in
+ * [k_lo, k_hi) for which idx = step (k - k_lo) + offset lies in [0, n_x) and
+ * d_x[idx] > threshold (d_x: device int32 [n_x], e.g. fh_bin_counts with
+ * step 1, or fh_line_counts with step K_f and offset K_f k_lo - b0). */
+fh_status fh_veto_bins(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi, const int32_t *d_x,
+                       int64_t n_x, int32_t step, int64_t offset, double threshold, void *stream,
+                       fh_peakmap **out);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /* A continuous-batching request server over one context.  Requests

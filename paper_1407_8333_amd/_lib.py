@@ -74,6 +74,11 @@ class fh_coarse_cand(ctypes.Structure):
                 ("beta", ctypes.c_double), ("dlambda", ctypes.c_double), ("dbeta", ctypes.c_double)]
 
 
+class fh_gross(ctypes.Structure):
+    _fields_ = [("t_origin", ctypes.c_double), ("dt_h", ctypes.c_double), ("df_h", ctypes.c_double),
+                ("c0", ctypes.c_int64), ("n_t", ctypes.c_int32), ("n_f", ctypes.c_int32)]
+
+
 class fh_refine_opts(ctypes.Structure):
     _fields_ = [("kf", ctypes.c_int32), ("k_fdot", ctypes.c_int32), ("k_sky", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("dfdot", ctypes.c_double), ("t0", ctypes.c_double),
@@ -117,6 +122,13 @@ _PROTOS = {
                             ctypes.c_int),
     "fh_peakmap_slice": ([P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)], ctypes.c_int),
     "fh_refine": ([P, P, ctypes.c_int32, P, ctypes.POINTER(fh_refine_opts), P, P, P], ctypes.c_int),
+    "fh_gross_histogram": ([P, P, ctypes.POINTER(fh_gross), P, P], ctypes.c_int),
+    "fh_clean_gross": ([P, P, ctypes.POINTER(fh_gross), ctypes.c_double, P, P, ctypes.POINTER(P)], ctypes.c_int),
+    "fh_bin_counts": ([P, P, ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int),
+    "fh_robust_stats": ([P, P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
+    "fh_line_counts": ([P, P, ctypes.POINTER(fh_grid), P, P], ctypes.c_int),
+    "fh_veto_bins": ([P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                      ctypes.c_double, P, ctypes.POINTER(P)], ctypes.c_int),
     "fh_server_create": ([P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)],
                          ctypes.c_int),
     "fh_server_submit": ([P, ctypes.POINTER(fh_request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -197,3 +209,9 @@ fh_peakmap_download = _fwd("fh_peakmap_download")
 fh_peakmap_shape = _fwd("fh_peakmap_shape")
 fh_peakmap_slice = _fwd("fh_peakmap_slice")
 fh_refine = _fwd("fh_refine")
+fh_gross_histogram = _fwd("fh_gross_histogram")
+fh_clean_gross = _fwd("fh_clean_gross")
+fh_bin_counts = _fwd("fh_bin_counts")
+fh_robust_stats = _fwd("fh_robust_stats")
+fh_line_counts = _fwd("fh_line_counts")
+fh_veto_bins = _fwd("fh_veto_bins")

@@ -133,18 +133,23 @@ class DevicePeakmap:
         check(_lib.fh_peakmap_download(self.ctx.handle, self.handle, off.ctypes.data, bins.ctypes.data))
         return off, bins[: int(off[-1])]
 
+    @classmethod
+    def wrap(cls, ctx: "Context", handle) -> "DevicePeakmap":
+        """Take ownership of a peakmap handle returned by the library."""
+        q = cls.__new__(cls)
+        q.ctx = ctx
+        q.handle = handle
+        n, p = ctypes.c_int32(), ctypes.c_int64()
+        check(_lib.fh_peakmap_shape(handle, ctypes.byref(n), ctypes.byref(p)))
+        q.n_fft, q.n_peaks = n.value, p.value
+        return q
+
     def slice(self, k_lo: int, k_hi: int, stream=None) -> "DevicePeakmap":
         """The peaks with natural bin in [k_lo, k_hi) (fh_peakmap_slice)."""
-        q = DevicePeakmap.__new__(DevicePeakmap)
-        q.ctx = self.ctx
         h = ctypes.c_void_p()
         check(_lib.fh_peakmap_slice(self.ctx.handle, self.handle, int(k_lo), int(k_hi), _stream(stream),
                                     ctypes.byref(h)))
-        q.handle = h
-        n, p = ctypes.c_int32(), ctypes.c_int64()
-        check(_lib.fh_peakmap_shape(h, ctypes.byref(n), ctypes.byref(p)))
-        q.n_fft, q.n_peaks = n.value, p.value
-        return q
+        return DevicePeakmap.wrap(self.ctx, h)
 
     @property
     def nbytes(self) -> int:

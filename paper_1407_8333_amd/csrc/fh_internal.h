@@ -124,6 +124,31 @@ hipError_t launch_slice(int32_t n_fft, const int64_t *offsets, const int32_t *bi
 // best of the first candidates of each refined direction, per coarse candidate
 hipError_t launch_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate *cands, const double *params,
                               const double *lamb, fh_refined *out, hipStream_t st);
+// peakmap cleaning
+hipError_t launch_gross_hist(int32_t n_fft, const int64_t *offsets, const int32_t *bins, const double *t,
+                             double t_fft, const fh_gross &geo, int32_t *hist, hipStream_t st);
+// filter of the peaks of a peakmap (mode 0: gross cells over thr; mode 1:
+// natural bins whose statistic exceeds thr); phase 0 counts survivors per
+// FFT and scans them into out_offsets, phase 1 packs the survivors
+struct FilterSpec {
+    int mode;
+    const double *t;
+    double t_fft;
+    fh_gross geo;
+    const int32_t *hist;
+    int32_t k_lo, k_hi, step;
+    int64_t offset, n_x;
+    const int32_t *x;
+    double thr;
+};
+hipError_t launch_filter(int32_t n_fft, const int64_t *offsets, const int32_t *bins, const FilterSpec &spec,
+                         int32_t *counts, int64_t *out_offsets, int32_t *out_bins, int phase, hipStream_t st);
+hipError_t launch_bin_counts(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo,
+                             int32_t k_hi, int32_t *counts, hipStream_t st);
+// robust statistic: hist needs 2 x_max + 1 entries; out[0] = m1, out[1] = m2
+hipError_t launch_robust(const int32_t *x, int32_t n, int32_t x_max, int32_t *hist, int64_t *s2, double *out,
+                         int32_t *err, hipStream_t st);
+hipError_t launch_colmax_values(const unsigned long long *colmax, int32_t nf, int32_t *out, hipStream_t st);
 int tile_lds_bytes(int W, int kf);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).
 hipError_t init_kernel_attributes();

@@ -1302,6 +1302,189 @@ __global__ void k_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate 
     out[c] = r;
 }
 
+// ----------------------------------------------------------------------------
+// peakmap cleaning
+
+// Filters on the peaks of a peakmap: mode 0 drops the peaks of gross cells
+// holding more than thr peaks; mode 1 drops the peaks of natural bins k in
+// [k_lo, k_hi) whose statistic x[step (k - k_lo) + offset] exceeds thr.
+struct PeakFilter {
+    int mode;
+    // mode 0
+    const double *t;
+    double t_origin, dt_h, B;  // B = df_h T_FFT
+    int64_t c0;
+    int32_t n_t, n_f;
+    const int32_t *hist;
+    // mode 1
+    int32_t k_lo, k_hi, step;
+    int64_t offset, n_x;
+    const int32_t *x;
+    double thr;
+};
+
+__device__ __forceinline__ int gross_time_cell(const PeakFilter &f, int i) {
+    return (int)floor((f.t[i] - f.t_origin) / f.dt_h);
+}
+
+// frequency cell of natural bin k, -1 when outside [0, n_f)
+__device__ __forceinline__ int64_t gross_freq_cell(const PeakFilter &f, int32_t k) {
+    const int64_t c = (int64_t)floor((double)k / f.B) - f.c0;
+    return c >= 0 && c < f.n_f ? c : -1;
+}
+
+__device__ __forceinline__ bool filter_drop(const PeakFilter &f, int ct, int32_t k) {
+    if (f.mode == 0) {
+        if (ct < 0 || ct >= f.n_t) return false;
+        const int64_t cf = gross_freq_cell(f, k);
+        return cf >= 0 && (double)f.hist[(int64_t)ct * f.n_f + cf] > f.thr;
+    }
+    if (k < f.k_lo || k >= f.k_hi) return false;
+    const int64_t idx = (int64_t)f.step * (k - f.k_lo) + f.offset;
+    return idx >= 0 && idx < f.n_x && (double)f.x[idx] > f.thr;
+}
+
+// one wave per FFT: cells of its peaks counted into the gross histogram
+__global__ void __launch_bounds__(256) k_gross_hist(int32_t n_fft, const int64_t *__restrict__ offsets,
+                                                    const int32_t *__restrict__ bins, PeakFilter f,
+                                                    int32_t *__restrict__ hist) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_fft) return;
+    const int ct = gross_time_cell(f, i);
+    if (ct < 0 || ct >= f.n_t) return;
+    for (int64_t p = offsets[i] + lane; p < offsets[i + 1]; p += 64) {
+        const int64_t cf = gross_freq_cell(f, bins[p]);
+        if (cf >= 0) atomicAdd(hist + (int64_t)ct * f.n_f + cf, 1);
+    }
+}
+
+// one wave per FFT: surviving peaks counted
+__global__ void __launch_bounds__(256) k_filter_count(int32_t n_fft, const int64_t *__restrict__ offsets,
+                                                      const int32_t *__restrict__ bins, PeakFilter f,
+                                                      int32_t *__restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_fft) return;
+    const int ct = f.mode == 0 ? gross_time_cell(f, i) : 0;
+    int kept = 0;
+    for (int64_t p = offsets[i] + lane; p < offsets[i + 1]; p += 64) kept += filter_drop(f, ct, bins[p]) ? 0 : 1;
+    for (int o = 32; o >= 1; o >>= 1) kept += __shfl_xor(kept, o);
+    if (lane == 0) counts[i] = kept;
+}
+
+// one wave per FFT: surviving peaks packed in order
+__global__ void __launch_bounds__(256) k_filter_pack(int32_t n_fft, const int64_t *__restrict__ offsets,
+                                                     const int32_t *__restrict__ bins, PeakFilter f,
+                                                     const int64_t *__restrict__ out_offsets,
+                                                     int32_t *__restrict__ out_bins) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_fft) return;
+    const int ct = f.mode == 0 ? gross_time_cell(f, i) : 0;
+    int64_t dst = out_offsets[i];
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t pb = offsets[i]; pb < offsets[i + 1]; pb += 64) {
+        const int64_t p = pb + lane;
+        const bool in = p < offsets[i + 1];
+        const int32_t k = in ? bins[p] : 0;
+        const bool keep = in && !filter_drop(f, ct, k);
+        const uint64_t m = __ballot(keep);
+        if (keep) out_bins[dst + __popcll(m & below)] = k;
+        dst += __popcll(m);
+    }
+}
+
+// one wave per FFT: peaks per natural bin in [k_lo, k_hi)
+__global__ void __launch_bounds__(256) k_bin_counts(int32_t n_fft, const int64_t *__restrict__ offsets,
+                                                    const int32_t *__restrict__ bins, int32_t k_lo,
+                                                    int32_t k_hi, int32_t *__restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_fft) return;
+    for (int64_t p = offsets[i] + lane; p < offsets[i + 1]; p += 64) {
+        const int32_t k = bins[p];
+        if (k >= k_lo && k < k_hi) atomicAdd(counts + (k - k_lo), 1);
+    }
+}
+
+// value histograms for the robust statistic: pass 0 counts x, pass 1 counts
+// |2 x - s| (s = twice the median, an integer)
+__global__ void k_value_hist(const int32_t *__restrict__ x, int32_t n, int32_t x_max, int pass,
+                             const int64_t *__restrict__ s2, int32_t *__restrict__ hist,
+                             int32_t *__restrict__ err) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int32_t v = x[e];
+    if (v < 0 || v > x_max) {
+        atomicOr(err, 1);
+        return;
+    }
+    if (pass == 0) {
+        atomicAdd(hist + v, 1);
+    } else {
+        int64_t d = 2 * (int64_t)v - s2[0];
+        d = d < 0 ? -d : d;
+        if (d <= 2 * (int64_t)x_max) atomicAdd(hist + d, 1);
+    }
+}
+
+// One block: the values at 1-based ranks ra and rb of a value histogram of
+// m bins; writes their sum to s2[0] and, for pass 0, m1 = sum / 2 to out[0],
+// for pass 1, m2 = sum / 4 / 0.6745 to out[1].
+__global__ void __launch_bounds__(1024) k_rank_pick(const int32_t *__restrict__ hist, int32_t m, int64_t ra,
+                                                    int64_t rb, int pass, int64_t *__restrict__ s2,
+                                                    double *__restrict__ out) {
+    __shared__ int64_t part[1024];
+    __shared__ int32_t val[2];
+    const int tid = threadIdx.x;
+    if (tid < 2) val[tid] = 0;  // stays 0 for a rank past the total (invalid data)
+    const int chunk = (m + 1023) / 1024;
+    const int v0 = tid * chunk, v1 = min(v0 + chunk, m);
+    int64_t sum = 0;
+    for (int v = v0; v < v1; ++v) sum += hist[v];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+        const int64_t a = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += a;
+        __syncthreads();
+    }
+    const int64_t before = part[tid] - sum;
+    for (int q = 0; q < 2; ++q) {
+        const int64_t r = q == 0 ? ra : rb;
+        if (r > before && r <= before + sum) {
+            int64_t c = before;
+            for (int v = v0; v < v1; ++v) {
+                c += hist[v];
+                if (c >= r) {
+                    val[q] = v;
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int64_t t = (int64_t)val[0] + (int64_t)val[1];
+        if (pass == 0) {
+            s2[0] = t;
+            out[0] = 0.5 * (double)t;
+        } else {
+            // median of |x - m1| = (t / 2) / 2: both halves exact
+            out[1] = 0.5 * (0.5 * (double)val[0] + 0.5 * (double)val[1]) / 0.6745;
+        }
+    }
+}
+
+// fine-bin counts of a column-maximum buffer (value << 32 | ~row)
+__global__ void k_colmax_values(const unsigned long long *__restrict__ colmax, int32_t nf,
+                                int32_t *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nf) out[b] = (int32_t)(colmax[b] >> 32);
+}
+
 }  // namespace
 
 hipError_t launch_slice(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo, int32_t k_hi,
@@ -1320,6 +1503,82 @@ hipError_t launch_refine_pick(int32_t n_cand, int32_t n_dir, const fh_candidate 
                               const double *lamb, fh_refined *out, hipStream_t st) {
     if (n_cand <= 0) return hipSuccess;
     k_refine_pick<<<grid_for(n_cand, 64), 64, 0, st>>>(n_cand, n_dir, cands, params, lamb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gross_hist(int32_t n_fft, const int64_t *offsets, const int32_t *bins, const double *t,
+                             double t_fft, const fh_gross &geo, int32_t *hist, hipStream_t st) {
+    hipError_t e = launch_fill_i32(hist, (int64_t)geo.n_t * geo.n_f, 0, st);
+    if (e != hipSuccess || n_fft == 0) return e;
+    PeakFilter f{};
+    f.mode = 0;
+    f.t = t;
+    f.t_origin = geo.t_origin;
+    f.dt_h = geo.dt_h;
+    f.B = geo.df_h * t_fft;
+    f.c0 = geo.c0;
+    f.n_t = geo.n_t;
+    f.n_f = geo.n_f;
+    k_gross_hist<<<(n_fft + 3) / 4, 256, 0, st>>>(n_fft, offsets, bins, f, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(int32_t n_fft, const int64_t *offsets, const int32_t *bins, const FilterSpec &spec,
+                         int32_t *counts, int64_t *out_offsets, int32_t *out_bins, int phase, hipStream_t st) {
+    PeakFilter f{};
+    f.mode = spec.mode;
+    f.t = spec.t;
+    f.t_origin = spec.geo.t_origin;
+    f.dt_h = spec.geo.dt_h;
+    f.B = spec.geo.df_h * spec.t_fft;
+    f.c0 = spec.geo.c0;
+    f.n_t = spec.geo.n_t;
+    f.n_f = spec.geo.n_f;
+    f.hist = spec.hist;
+    f.k_lo = spec.k_lo;
+    f.k_hi = spec.k_hi;
+    f.step = spec.step;
+    f.offset = spec.offset;
+    f.n_x = spec.n_x;
+    f.x = spec.x;
+    f.thr = spec.thr;
+    if (n_fft == 0) return hipSuccess;
+    if (phase == 0) {
+        k_filter_count<<<(n_fft + 3) / 4, 256, 0, st>>>(n_fft, offsets, bins, f, counts);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_pm_scan<<<1, 1024, 0, st>>>(n_fft, counts, out_offsets);
+    } else {
+        k_filter_pack<<<(n_fft + 3) / 4, 256, 0, st>>>(n_fft, offsets, bins, f, out_offsets, out_bins);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_counts(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo,
+                             int32_t k_hi, int32_t *counts, hipStream_t st) {
+    hipError_t e = launch_fill_i32(counts, (int64_t)k_hi - k_lo, 0, st);
+    if (e != hipSuccess || n_fft == 0) return e;
+    k_bin_counts<<<(n_fft + 3) / 4, 256, 0, st>>>(n_fft, offsets, bins, k_lo, k_hi, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_robust(const int32_t *x, int32_t n, int32_t x_max, int32_t *hist, int64_t *s2, double *out,
+                         int32_t *err, hipStream_t st) {
+    const int64_t ra = (int64_t)(n + 1) / 2, rb = (int64_t)n / 2 + 1;  // odd n: both the middle
+    for (int pass = 0; pass < 2; ++pass) {
+        const int32_t m = pass == 0 ? x_max + 1 : 2 * x_max + 1;
+        hipError_t e = launch_fill_i32(hist, m, 0, st);
+        if (e != hipSuccess) return e;
+        k_value_hist<<<grid_for(n, 256), 256, 0, st>>>(x, n, x_max, pass, s2, hist, err);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_rank_pick<<<1, 1024, 0, st>>>(hist, m, ra, rb, pass, s2, out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_colmax_values(const unsigned long long *colmax, int32_t nf, int32_t *out, hipStream_t st) {
+    k_colmax_values<<<grid_for(nf, 256), 256, 0, st>>>(colmax, nf, out);
     return hipGetLastError();
 }
 

@@ -141,6 +141,8 @@ struct fh_ctx {
     DevBuf err;
     // refinement: sliced peakmap and per-call scratch
     DevBuf rf_offsets, rf_bins, rf_t, rf_v, rf_first, rf_counts, rf_cands, rf_aux;
+    // cleaning: robust-statistic histogram, its rank sum and results
+    DevBuf cl_hist, cl_s2, cl_out;
     // autotuned tile width per problem shape
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
     // captured searches (fh_options.use_graph), keyed by every argument and
@@ -524,6 +526,69 @@ fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sk
 
 }  // namespace
 
+// peakmap cleaning helpers
+namespace {
+
+fh_status check_gross(const fh_gross *geo) {
+    if (!geo) return fail(FH_E_INVALID, "gross geometry is NULL");
+    if (!(geo->dt_h > 0) || !(geo->df_h > 0) || !std::isfinite(geo->dt_h) || !std::isfinite(geo->df_h) ||
+        !std::isfinite(geo->t_origin))
+        return fail(FH_E_INVALID, "gross cells need finite dt_h > 0, df_h > 0 and t_origin");
+    if (geo->n_t < 1 || geo->n_f < 1 || (int64_t)geo->n_t * geo->n_f > ((int64_t)1 << 31))
+        return fail(FH_E_INVALID, "gross histogram of %d x %d cells", geo->n_t, geo->n_f);
+    return FH_OK;
+}
+
+// A new peakmap holding the peaks of pm that `spec` keeps.
+fh_status filter_peakmap(fh_ctx *ctx, const fh_peakmap *pm, const FilterSpec &spec, hipStream_t st,
+                         fh_peakmap **out) {
+    fh_status s;
+    const int32_t N = pm->n_fft;
+    if ((s = ctx->rf_counts.ensure(4 * (size_t)std::max(1, N), st))) return s;
+    fh_peakmap *q = new fh_peakmap(*pm);
+    q->d_offsets = nullptr;
+    q->d_bins = nullptr;
+    q->d_t = nullptr;
+    q->d_v = nullptr;
+    const size_t b_off = 8 * (size_t)(N + 1);
+    if (hipMalloc(&q->d_offsets, b_off) != hipSuccess || hipMalloc(&q->d_t, 8 * (size_t)N) != hipSuccess ||
+        hipMalloc(&q->d_v, 24 * (size_t)N) != hipSuccess) {
+        fh_peakmap_release(ctx, q);
+        return fail(FH_E_NOMEM, "device allocation for the cleaned peakmap failed");
+    }
+    std::vector<int64_t> h_off((size_t)N + 1, 0);
+    hipError_t e = hipSuccess;
+    if (N > 0) {
+        e = launch_filter(N, pm->d_offsets, pm->d_bins, spec, (int32_t *)ctx->rf_counts.ptr, q->d_offsets,
+                          nullptr, 0, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_off.data(), q->d_offsets, b_off, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    } else {
+        e = hipMemcpyAsync(q->d_offsets, h_off.data(), b_off, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    const int64_t P = e == hipSuccess ? h_off[N] : 0;
+    if (e == hipSuccess && hipMalloc(&q->d_bins, 4 * (size_t)std::max<int64_t>(1, P)) != hipSuccess)
+        e = hipErrorOutOfMemory;
+    if (e == hipSuccess && N > 0)
+        e = launch_filter(N, pm->d_offsets, pm->d_bins, spec, nullptr, q->d_offsets, q->d_bins, 1, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->d_t, pm->d_t, 8 * (size_t)N, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->d_v, pm->d_v, 24 * (size_t)N, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        fh_peakmap_release(ctx, q);
+        return fail(e == hipErrorOutOfMemory ? FH_E_NOMEM : FH_E_DEVICE, "filtering the peakmap failed: %s",
+                    hipGetErrorString(e));
+    }
+    q->n_peaks = P;
+    q->max_per_fft = 0;
+    for (int32_t i = 0; i < N; ++i) q->max_per_fft = std::max<int32_t>(q->max_per_fft, (int32_t)(h_off[i + 1] - h_off[i]));
+    q->bytes = (int64_t)(b_off + 4 * (size_t)std::max<int64_t>(1, P) + 32 * (size_t)N);
+    *out = q;
+    return FH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *fh_version(void) { return "fh-mi355x 0.1 (gfx950)"; }
@@ -572,7 +637,7 @@ void fh_ctx_destroy(fh_ctx *ctx) {
     ctx->main_ws.release();
     ctx->err.release();
     for (DevBuf *b : {&ctx->rf_offsets, &ctx->rf_bins, &ctx->rf_t, &ctx->rf_v, &ctx->rf_first, &ctx->rf_counts,
-                      &ctx->rf_cands, &ctx->rf_aux})
+                      &ctx->rf_cands, &ctx->rf_aux, &ctx->cl_hist, &ctx->cl_s2, &ctx->cl_out})
         b->release();
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
@@ -944,6 +1009,113 @@ fh_status fh_refine(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_cand, const fh_
     return FH_OK;
 }
 
+
+// ---- peakmap cleaning ----
+
+fh_status fh_gross_histogram(fh_ctx *ctx, const fh_peakmap *pm, const fh_gross *geo, int32_t *d_hist,
+                             void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if ((s = check_gross(geo))) return s;
+    if (!d_hist) return fail(FH_E_INVALID, "histogram pointer is NULL");
+    HIP_OK(launch_gross_hist(pm->n_fft, pm->d_offsets, pm->d_bins, pm->d_t, pm->t_fft, *geo, d_hist,
+                             (hipStream_t)stream));
+    return FH_OK;
+}
+
+fh_status fh_clean_gross(fh_ctx *ctx, const fh_peakmap *pm, const fh_gross *geo, double threshold,
+                         int32_t *d_hist, void *stream, fh_peakmap **out) {
+    fh_status s;
+    if (!out) return fail(FH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (std::isnan(threshold)) return fail(FH_E_INVALID, "threshold is NaN");
+    if ((s = fh_gross_histogram(ctx, pm, geo, d_hist, stream))) return s;
+    FilterSpec f{};
+    f.mode = 0;
+    f.t = pm->d_t;
+    f.t_fft = pm->t_fft;
+    f.geo = *geo;
+    f.hist = d_hist;
+    f.thr = threshold;
+    return filter_peakmap(ctx, pm, f, (hipStream_t)stream, out);
+}
+
+fh_status fh_bin_counts(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi, int32_t *d_counts,
+                        void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if (k_lo < 0 || k_hi <= k_lo) return fail(FH_E_INVALID, "need 0 <= k_lo < k_hi");
+    if (!d_counts) return fail(FH_E_INVALID, "counts pointer is NULL");
+    HIP_OK(launch_bin_counts(pm->n_fft, pm->d_offsets, pm->d_bins, k_lo, k_hi, d_counts, (hipStream_t)stream));
+    return FH_OK;
+}
+
+fh_status fh_robust_stats(fh_ctx *ctx, const int32_t *d_x, int32_t n, int32_t x_max, double out[2],
+                          void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (!d_x || !out) return fail(FH_E_INVALID, "data or output pointer is NULL");
+    if (n < 1) return fail(FH_E_INVALID, "robust statistic of %d values", n);
+    if (x_max < 0 || x_max > (1 << 28)) return fail(FH_E_INVALID, "x_max=%d outside 0..2^28", x_max);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = ctx->cl_hist.ensure(4 * (2 * (size_t)x_max + 1), st)) || (s = ctx->cl_s2.ensure(8, st)) ||
+        (s = ctx->cl_out.ensure(16, st)) || (s = ctx->err.ensure(4, st)))
+        return s;
+    int32_t *err = (int32_t *)ctx->err.ptr;
+    HIP_OK(launch_fill_i32(err, 1, 0, st));
+    HIP_OK(launch_robust(d_x, n, x_max, (int32_t *)ctx->cl_hist.ptr, (int64_t *)ctx->cl_s2.ptr,
+                         (double *)ctx->cl_out.ptr, err, st));
+    int32_t h_err = 0;
+    double h_out[2];
+    HIP_OK(hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(h_out, ctx->cl_out.ptr, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (h_err) return fail(FH_E_INVALID, "a value lies outside [0, x_max=%d]", x_max);
+    out[0] = h_out[0];
+    out[1] = h_out[1];
+    return FH_OK;
+}
+
+fh_status fh_line_counts(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int32_t *d_out, void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if ((s = check_grid(pm, g))) return s;
+    if (!d_out) return fail(FH_E_INVALID, "output pointer is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, 0));
+    ChunkBufs b;
+    if ((s = ensure_workspace(ctx, pm, g, p, 1, 1, false, st, b))) return s;
+    const double zero[3] = {0.0, 0.0, 0.0};  // v . n = 0: no Doppler correction
+    if ((s = upload_sky(ctx, zero, 1, b, st))) return s;
+    if ((s = run_search(ctx, pm, g, p, 1, 1, nullptr, 0, FH_SCHED_PERSISTENT, nullptr, nullptr, b, st))) return s;
+    HIP_OK(launch_colmax_values(b.colmax, g->nf, d_out, st));
+    return FH_OK;
+}
+
+fh_status fh_veto_bins(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t k_hi, const int32_t *d_x,
+                       int64_t n_x, int32_t step, int64_t offset, double threshold, void *stream,
+                       fh_peakmap **out) {
+    fh_status s;
+    if (!out) return fail(FH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((s = check_ctx(ctx))) return s;
+    if (!pm) return fail(FH_E_INVALID, "peakmap is NULL");
+    if (k_lo < 0 || k_hi <= k_lo) return fail(FH_E_INVALID, "need 0 <= k_lo < k_hi");
+    if (!d_x || n_x < 1) return fail(FH_E_INVALID, "statistic array is NULL or empty");
+    if (std::isnan(threshold)) return fail(FH_E_INVALID, "threshold is NaN");
+    FilterSpec f{};
+    f.mode = 1;
+    f.k_lo = k_lo;
+    f.k_hi = k_hi;
+    f.step = step;
+    f.offset = offset;
+    f.n_x = n_x;
+    f.x = d_x;
+    f.thr = threshold;
+    return filter_peakmap(ctx, pm, f, (hipStream_t)stream, out);
+}
 
 fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int32_t tile_bins,
                         fh_plan_info *out) {
