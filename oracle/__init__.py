@@ -52,6 +52,11 @@ def _load():
             lib.fho_hough_map.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
                                           f64, f64, f64, i32, i32, P]
             lib.fho_hough_map.restype = ctypes.c_int
+            lib.fho_hough_map_mode.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
+                                               f64, f64, f64, i32, i32, i32, f64, P]
+            lib.fho_hough_map_mode.restype = ctypes.c_int
+            lib.fho_shift_center.argtypes = [i32, i32, f64, f64]
+            lib.fho_shift_center.restype = i64
             lib.fho_candidates.argtypes = [P, i32, i32, i32, i32, i32, P, P]
             lib.fho_candidates.restype = i32
             lib.fho_shifts.argtypes = [i32, P, f64, f64, i32, f64, f64, P, P]
@@ -72,12 +77,21 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def hough_map(pm, grid, nhat, weights=None, rows=None, threads=None) -> np.ndarray:
+def shift_reference(grid, t_fft: float) -> float:
+    """Default reference frequency of the per-FFT shift variant: the centre
+    of the map's band, (b0 + nf / 2) / (K_f T_FFT)."""
+    return (float(grid.b0) + 0.5 * float(grid.nf)) / (float(grid.kf) * float(t_fft))
+
+
+def hough_map(pm, grid, nhat, weights=None, rows=None, threads=None, doppler: str = "exact",
+              f_ref=None) -> np.ndarray:
     """FP64 Hough map [ns][nf] of one sky direction.
 
     pm: peakmap (t_fft, t, v, offsets, bins); grid: kf, b0, nf, ns, fdot0,
     dfdot, t0; nhat: unit vector; weights: per-FFT weights or None; rows:
-    (lo, hi) to compute a row range only (other rows are returned as 0).
+    (lo, hi) to compute a row range only (other rows are returned as 0);
+    doppler: "exact" (per peak) or "shift" (per FFT at f_ref, by default the
+    band centre).
     """
     lib = _load()
     if threads is not None:
@@ -90,11 +104,14 @@ def hough_map(pm, grid, nhat, weights=None, rows=None, threads=None) -> np.ndarr
     w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     lo, hi = (0, grid.ns) if rows is None else rows
     out = np.zeros((grid.ns, grid.nf), dtype=np.float64)
-    rc = lib.fho_hough_map(int(t.shape[0]), _ptr(off), _ptr(bins), _ptr(t), _ptr(v),
-                           float(pm.t_fft), _ptr(n), None if w is None else _ptr(w),
-                           int(grid.kf), int(grid.b0), int(grid.nf), int(grid.ns),
-                           float(grid.fdot0), float(grid.dfdot), float(grid.t0),
-                           int(lo), int(hi), _ptr(out))
+    if doppler not in ("exact", "shift"):
+        raise ValueError("doppler must be 'exact' or 'shift'")
+    fr = shift_reference(grid, pm.t_fft) if f_ref is None else float(f_ref)
+    rc = lib.fho_hough_map_mode(int(t.shape[0]), _ptr(off), _ptr(bins), _ptr(t), _ptr(v),
+                                float(pm.t_fft), _ptr(n), None if w is None else _ptr(w),
+                                int(grid.kf), int(grid.b0), int(grid.nf), int(grid.ns),
+                                float(grid.fdot0), float(grid.dfdot), float(grid.t0),
+                                int(lo), int(hi), 1 if doppler == "shift" else 0, fr, _ptr(out))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out
@@ -129,6 +146,11 @@ def inv_doppler(pm, nhat):
     nh = np.ascontiguousarray(np.asarray(nhat, dtype=np.float64).reshape(3))
     lib.fho_inv_doppler(n, _ptr(v), _ptr(nh), _ptr(r))
     return r
+
+
+def shift_center(k, kf, q, r):
+    """Corrected centre of the per-FFT shift variant (q: reference in fine bins)."""
+    return int(_load().fho_shift_center(int(k), int(kf), float(q), float(r)))
 
 
 def center(k, kf, r):

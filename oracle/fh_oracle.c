@@ -30,6 +30,13 @@
  * the order written and never contracted into FMAs (build with
  * -ffp-contract=off).
  *
+ * Per-FFT shift variant (the Doppler removal read as a plain shift of each
+ * FFT's bins, computed at one reference frequency f_ref for the whole band):
+ *   q      = ((double)K_f * T_FFT) * f_ref                 (reference, fine bins)
+ *   X      = K_f*k*Q - llrint((q * (1 - r)) * Q)
+ * which equals the exact centre at k = f_ref T_FFT and drifts from it by
+ * (K_f k - q)(1 - r) fine bins elsewhere.
+ *
  * The oracle fills every touched fine bin directly (K_f additions per peak and
  * row), accumulating in double; it is deliberately slow.
  */
@@ -79,17 +86,24 @@ int64_t fho_center(int32_t k, int32_t kf, double r)
     return (int64_t)floor(x);
 }
 
+/* Corrected peak centre of the per-FFT shift variant. */
+int64_t fho_shift_center(int32_t k, int32_t kf, double q, double r)
+{
+    return (int64_t)kf * (int64_t)k * QI - llrint((q * (1.0 - r)) * QD);
+}
+
 /*
  * Hough map of one sky direction, rows [row_lo, row_hi) only (the other rows
  * of `out` are left untouched).  out is [ns][nf] row-major, double, and is
  * zeroed on the selected rows first.  w may be NULL (all weights 1).
+ * shift = 0: exact per-peak Doppler correction; 1: per-FFT shift at f_ref.
  * Returns 0, or -1 on invalid arguments.
  */
-int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
-                  const double *t, const double *v, double t_fft, const double *nhat,
-                  const double *w, int32_t kf, int64_t b0, int32_t nf, int32_t ns,
-                  double fdot0, double dfdot, double t0, int32_t row_lo, int32_t row_hi,
-                  double *out)
+int fho_hough_map_mode(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
+                       const double *t, const double *v, double t_fft, const double *nhat,
+                       const double *w, int32_t kf, int64_t b0, int32_t nf, int32_t ns,
+                       double fdot0, double dfdot, double t0, int32_t row_lo, int32_t row_hi,
+                       int32_t shift_mode, double f_ref, double *out)
 {
     if (n_fft < 0 || kf < 1 || nf < 0 || ns < 0 || row_lo < 0 || row_hi > ns || row_lo > row_hi)
         return -1;
@@ -105,9 +119,11 @@ int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
     fho_shifts(n_fft, t, t0, t_fft, kf, fdot0, dfdot, g0, dg);
     fho_inv_doppler(n_fft, v, nhat, r);
     /* stripe left edge at fdot = 0: E = X - b0*Q - K_f*Q/2 */
+    const double q = ((double)kf * t_fft) * f_ref;
     for (int32_t i = 0; i < n_fft; ++i)
         for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p)
-            edge[p] = fho_center(bins[p], kf, r[i]) - b0 * QI - (int64_t)kf * (QI / 2);
+            edge[p] = (shift_mode ? fho_shift_center(bins[p], kf, q, r[i]) : fho_center(bins[p], kf, r[i])) -
+                      b0 * QI - (int64_t)kf * (QI / 2);
 
     const int64_t width = (int64_t)kf * QI;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -131,6 +147,16 @@ int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
     }
     free(g0); free(dg); free(r); free(edge);
     return 0;
+}
+
+int fho_hough_map(int32_t n_fft, const int64_t *offsets, const int32_t *bins,
+                  const double *t, const double *v, double t_fft, const double *nhat,
+                  const double *w, int32_t kf, int64_t b0, int32_t nf, int32_t ns,
+                  double fdot0, double dfdot, double t0, int32_t row_lo, int32_t row_hi,
+                  double *out)
+{
+    return fho_hough_map_mode(n_fft, offsets, bins, t, v, t_fft, nhat, w, kf, b0, nf, ns, fdot0, dfdot, t0,
+                              row_lo, row_hi, 0, 0.0, out);
 }
 
 /*
