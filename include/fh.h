@@ -163,6 +163,18 @@ fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
  * unknown name or value. */
 fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value);
 
+/* Doppler correction used by every later search of the context (Sec. "The
+ * frequency-Hough transform": removing the Doppler effect amounts to
+ * shifting each FFT's bins).  mode 0 (default): exact per peak, the centre
+ * X = floor(((double)(K_f k) r) 2^16) with r = 1 / (1 + v_i . n).  mode 1: one
+ * shift per FFT computed at the reference frequency f_ref [Hz] (f_ref <= 0:
+ * each map's band centre (b0 + nf / 2) / (K_f T_FFT)):
+ *   q = ((double)K_f * T_FFT) * f_ref,  X = K_f k 2^16 - llrint((q (1 - r)) 2^16)
+ * which is exact at f_ref and drifts by (K_f k - q)(1 - r) fine bins away
+ * from it (up to half the band times |v| natural bins).  FH_E_INVALID for
+ * another mode or a non-finite f_ref. */
+fh_status fh_ctx_set_doppler(fh_ctx *ctx, int32_t mode, double f_ref);
+
 /* ---- peakmaps ---------------------------------------------------------- */
 
 /* Validate a host peakmap and copy it to device memory owned by the returned

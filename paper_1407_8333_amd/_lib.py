@@ -106,6 +106,7 @@ _PROTOS = {
     "fh_ctx_destroy": ([P], None),
     "fh_ctx_check": ([P, P], ctypes.c_int),
     "fh_ctx_set_option": ([P, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
+    "fh_ctx_set_doppler": ([P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     "fh_peakmap_upload": ([P, ctypes.POINTER(fh_peakmap_desc), P, ctypes.POINTER(P)], ctypes.c_int),
     "fh_peakmap_release": ([P, P], None),
     "fh_peakmap_from_spectra": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, ctypes.c_int32,
@@ -209,6 +210,7 @@ fh_peakmap_download = _fwd("fh_peakmap_download")
 fh_peakmap_shape = _fwd("fh_peakmap_shape")
 fh_peakmap_slice = _fwd("fh_peakmap_slice")
 fh_refine = _fwd("fh_refine")
+fh_ctx_set_doppler = _fwd("fh_ctx_set_doppler")
 fh_gross_histogram = _fwd("fh_gross_histogram")
 fh_clean_gross = _fwd("fh_clean_gross")
 fh_bin_counts = _fwd("fh_bin_counts")

@@ -66,6 +66,12 @@ class Context:
     def set_option(self, name: str, value: int):
         check(_lib.fh_ctx_set_option(self.handle, name.encode(), int(value)))
 
+    def set_doppler(self, mode: str = "exact", f_ref: float = 0.0):
+        """Doppler correction of later searches: "exact" per peak, or "shift"
+        per FFT at f_ref Hz (0: each map's band centre) (fh_ctx_set_doppler)."""
+        m = {"exact": 0, "shift": 1}[mode]
+        check(_lib.fh_ctx_set_doppler(self.handle, m, float(f_ref)))
+
     def profile(self, enable: bool):
         check(_lib.fh_ctx_profile(self.handle, 1 if enable else 0))
 

@@ -84,7 +84,7 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
                        const WeightStats *ws, int32_t ws_stride, uint32_t *wq, uint32_t *Y32,
-                       hipStream_t st);
+                       int32_t shift_mode, double q, hipStream_t st);
 // fused stripe edges + weights + windows (LDS-staged edges of F FFTs per
 // workgroup); F = front_ffts_per_block(max peaks of one FFT), 0 when even one
 // FFT's edges do not fit (then use launch_prep + launch_windows)
@@ -96,7 +96,9 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
                         const int64_t *g0, const int64_t *dg, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
-                        int2 *win, hipStream_t st);
+                        int2 *win, int32_t shift_mode, double q, hipStream_t st);
+// shift_mode 1: Doppler correction as a per-FFT shift computed at the
+// reference q = (K_f T_FFT) f_ref fine bins (0: exact per peak)
 // window rows sorted by window size per tile-wave run (see k_sort_windows)
 hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t n_slots, const int2 *win,
                                int2 *wsorted, hipStream_t st);

@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_prep(
     const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
     int64_t *__restrict__ Y, const float *__restrict__ w, int32_t w_stride,
     const WeightStats *__restrict__ ws, int32_t ws_stride, uint32_t *__restrict__ wq,
-    uint32_t *__restrict__ Y32) {
+    uint32_t *__restrict__ Y32, int32_t shift_mode, double q) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int slot = blockIdx.y;
@@ -170,16 +170,22 @@ __global__ void __launch_bounds__(256) k_prep(
     d = d + vi[2] * n[2];
     d = 1.0 + d;
     const double r = 1.0 / d;
-    const int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+    int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+    if (shift_mode) c -= llrint((q * (1.0 - r)) * kQd);  // per-FFT shift at the reference
     // FFT i's edges start at offsets[i] + kYPad * i and are followed by kYPad
     // sentinels
     int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
     uint32_t *Ys32 = Y32 + (int64_t)slot * y_stride(n_peaks, n_fft) + (int64_t)kYPad * i;
     const int64_t e = offsets[i + 1];
     for (int64_t p = offsets[i] + lane; p < e; p += 64) {
-        double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
-        x = x * kQd;
-        const int64_t y = (int64_t)floor(x) + c;
+        int64_t y;
+        if (shift_mode) {
+            y = (int64_t)kf * (int64_t)bins[p] * kQ + c;
+        } else {
+            double x = (double)((int64_t)kf * (int64_t)bins[p]) * r;
+            x = x * kQd;
+            y = (int64_t)floor(x) + c;
+        }
         Ys[p] = y;
         Ys32[p] = (uint32_t)y;
     }
@@ -212,7 +218,7 @@ __global__ void __launch_bounds__(256) k_front(
     const int64_t *__restrict__ dg, uint32_t *__restrict__ Y, const float *__restrict__ w,
     int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
     uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
-    int2 *__restrict__ win) {
+    int2 *__restrict__ win, int32_t shift_mode, double q) {
     extern __shared__ int64_t ys[];
     __shared__ int64_t s_off[kFrontMaxF + 1];  // offsets of the block's FFTs
     __shared__ int64_t s_c[kFrontMaxF];        // per-FFT constant of the edge
@@ -236,8 +242,11 @@ __global__ void __launch_bounds__(256) k_front(
         d = d + vi[1] * n[1];
         d = d + vi[2] * n[2];
         d = 1.0 + d;
-        s_r[threadIdx.x] = 1.0 / d;
-        s_c[threadIdx.x] = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+        const double r = 1.0 / d;
+        s_r[threadIdx.x] = r;
+        int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+        if (shift_mode) c -= llrint((q * (1.0 - r)) * kQd);  // per-FFT shift at the reference
+        s_c[threadIdx.x] = c;
         if (w != nullptr) {
             const WeightStats wst = ws[(int64_t)slot * ws_stride];
             double wi = (double)w[(int64_t)slot * w_stride + i];
@@ -253,9 +262,14 @@ __global__ void __launch_bounds__(256) k_front(
         int l = 0;
         for (int64_t p = P0 + threadIdx.x; p < P1; p += blockDim.x) {
             while (s_off[l + 1] <= p) ++l;
-            double x = (double)((int64_t)kf * (int64_t)bins[p]) * s_r[l];
-            x = x * kQd;
-            const int64_t y = (int64_t)floor(x) + s_c[l];
+            int64_t y;
+            if (shift_mode) {
+                y = (int64_t)kf * (int64_t)bins[p] * kQ + s_c[l];
+            } else {
+                double x = (double)((int64_t)kf * (int64_t)bins[p]) * s_r[l];
+                x = x * kQd;
+                y = (int64_t)floor(x) + s_c[l];
+            }
             Yslot[p + (int64_t)kYPad * (f0 + l)] = (uint32_t)y;  // the tiles use the low word
             ys[p - P0 + (int64_t)kYPad * l] = y;
         }
@@ -1123,10 +1137,10 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
                        const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
                        const WeightStats *ws, int32_t ws_stride, uint32_t *wq, uint32_t *Y32,
-                       hipStream_t st) {
+                       int32_t shift_mode, double q, hipStream_t st) {
     dim3 grid((n_fft + 3) / 4, n_slots);
     k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, Y, w, w_stride,
-                                 ws, ws_stride, wq, Y32);
+                                 ws, ws_stride, wq, Y32, shift_mode, q);
     return hipGetLastError();
 }
 
@@ -1141,13 +1155,14 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
                         const int64_t *g0, const int64_t *dg, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
-                        int2 *win, hipStream_t st) {
+                        int2 *win, int32_t shift_mode, double q, hipStream_t st) {
     if (F < 1 || win_stride(n_fft) % F != 0) return hipErrorInvalidValue;
     dim3 grid(win_stride(n_fft) / F, n_slots);
     const size_t lds = ((size_t)F * (max_per_fft + kYPad) * 8 + 255) / 256 * 256;
     if (F > kFrontMaxF || lds > (size_t)kFrontLdsBytes) return hipErrorInvalidValue;
     k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
-                                               w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win);
+                                               w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win,
+                                               shift_mode, q);
     return hipGetLastError();
 }
 

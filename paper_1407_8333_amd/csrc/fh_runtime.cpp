@@ -138,6 +138,10 @@ struct fh_ctx {
     Workspace main_ws;
     Workspace *cur = &main_ws;  // workspace used by the launch sequences
     int32_t window_method = 2;  // peak windows: 0 binary searches, 1 sweep, 2 fused front
+    // Doppler correction: 0 exact per peak, 1 per-FFT shift at doppler_fref
+    // (<= 0: each map's band centre)
+    int32_t doppler_mode = 0;
+    double doppler_fref = 0.0;
     DevBuf err;
     // refinement: sliced peakmap and per-call scratch
     DevBuf rf_offsets, rf_bins, rf_t, rf_v, rf_first, rf_counts, rf_cands, rf_aux;
@@ -377,6 +381,14 @@ fh_status upload_sky(fh_ctx *ctx, const double *sky_host, int n_sky, const Chunk
 }
 
 // Shared front half of every path: shifts, weights, stripe edges, windows.
+// Reference of the per-FFT shift variant, in fine bins: (K_f T_FFT) f_ref.
+double shift_reference_bins(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g) {
+    const double f_ref = ctx->doppler_fref > 0
+                             ? ctx->doppler_fref
+                             : ((double)g->b0 + 0.5 * (double)g->nf) / ((double)g->kf * pm->t_fft);
+    return ((double)g->kf * pm->t_fft) * f_ref;
+}
+
 fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p,
                         int slots, const double *d_sky, const float *d_w, int w_stride,
                         const ChunkBufs &b, hipStream_t st) {
@@ -388,15 +400,18 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     if (weighted)
         HIP_OK(launch_weight_stats(pm->n_fft, n_vec, d_w, w_stride, pm->adjacent ? 2 : 1, b.ws, b.err, st));
     const int F = ctx->window_method == 2 ? front_ffts_per_block(pm->max_per_fft) : 0;
+    const int32_t sm = ctx->doppler_mode;
+    const double q = sm ? shift_reference_bins(ctx, pm, g) : 0.0;
     if (F > 0) {
         HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
                             g->b0, b.g0, b.dg, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
-                            p.nrbg, p.nbb, p.W, F, pm->max_per_fft, b.win, st));
+                            p.nrbg, p.nbb, p.W, F, pm->max_per_fft, b.win, sm, q, st));
         HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
         return FH_OK;
     }
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
-                       g->kf, g->b0, b.g0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, st));
+                       g->kf, g->b0, b.g0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, sm, q,
+                       st));
     HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
     HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
@@ -641,6 +656,16 @@ void fh_ctx_destroy(fh_ctx *ctx) {
         b->release();
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
+}
+
+fh_status fh_ctx_set_doppler(fh_ctx *ctx, int32_t mode, double f_ref) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if (mode != 0 && mode != 1) return fail(FH_E_INVALID, "Doppler mode must be 0 (exact) or 1 (per-FFT shift)");
+    if (!std::isfinite(f_ref)) return fail(FH_E_INVALID, "reference frequency is not finite");
+    ctx->doppler_mode = mode;
+    ctx->doppler_fref = f_ref;
+    return FH_OK;
 }
 
 fh_status fh_ctx_set_option(fh_ctx *ctx, const char *name, int64_t value) {
@@ -1194,7 +1219,8 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.wsort, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
         (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt,
-        (uint64_t)(uintptr_t)b.qctr, (uint64_t)(uintptr_t)b.Y64, (uint64_t)ctx->window_method};
+        (uint64_t)(uintptr_t)b.qctr, (uint64_t)(uintptr_t)b.Y64, (uint64_t)ctx->window_method,
+        (uint64_t)ctx->doppler_mode, bits(ctx->doppler_fref)};
     fh_ctx::GraphEntry *ge = nullptr;
     for (auto &e : ctx->graphs)
         if (e.key == key) ge = &e;
