@@ -54,6 +54,8 @@ def parse():
                     help="requests of the Poisson serving run (0 disables it)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured serving capacity")
+    ap.add_argument("--doppler", default="exact", choices=["exact", "shift"],
+                    help="Doppler correction: exact per peak (default) or one shift per FFT")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB moved by one plain device copy before the timed steps "
                          "(reference dispatch for hardware byte counters)")
@@ -232,6 +234,7 @@ def main():
     cells_per_sky = w.pm.n_peaks * grid.ns
     dev = torch.device("cuda:0")
     ctx = api.Context(0)
+    ctx.set_doppler(args.doppler)
     dpm = ctx.upload(w.pm)
     wt = None if w.weights is None else torch.as_tensor(w.weights, device=dev)
     out = torch.empty((n_sky, api.n_subbands(grid, sel), 2, 8), dtype=torch.int32, device=dev)
@@ -313,7 +316,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload),
                    "n_sky": n_sky, "n_fft": w.pm.n_fft, "n_peaks": w.pm.n_peaks,
                    "ns": grid.ns, "nf": grid.nf, "kf": grid.kf,
-                   "weighted": wt is not None, "schedule": "persistent",
+                   "weighted": wt is not None, "schedule": "persistent", "doppler": args.doppler,
                    "tile": [plan["tile_rows"], plan["tile_bins"]]},
         "p50_ms_per_step": pct(step_ms, 50),
         "p99_ms_per_step": pct(step_ms, 99),

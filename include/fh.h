@@ -419,6 +419,11 @@ fh_status fh_server_cancel(fh_server *srv, uint64_t id);
 fh_status fh_server_stats(const fh_server *srv, int32_t *queued, int32_t *running,
                           int32_t *finished, int64_t *bytes_in_flight);
 
+/* Admit and run every queued request and wait until none is running; their
+ * completions stay available to fh_server_poll.  FH_E_DEVICE if a wait
+ * fails. */
+fh_status fh_server_drain(fh_server *srv);
+
 /* Wait for all queued and running requests to finish, then free the server
  * (completions not yet polled are dropped).  NULL is a no-op. */
 void fh_server_destroy(fh_server *srv);

@@ -135,6 +135,7 @@ _PROTOS = {
     "fh_server_submit": ([P, ctypes.POINTER(fh_request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "fh_server_poll": ([P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "fh_server_cancel": ([P, ctypes.c_uint64], ctypes.c_int),
+    "fh_server_drain": ([P], ctypes.c_int),
     "fh_server_stats": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "fh_server_destroy": ([P], None),
@@ -210,6 +211,7 @@ fh_peakmap_download = _fwd("fh_peakmap_download")
 fh_peakmap_shape = _fwd("fh_peakmap_shape")
 fh_peakmap_slice = _fwd("fh_peakmap_slice")
 fh_refine = _fwd("fh_refine")
+fh_server_drain = _fwd("fh_server_drain")
 fh_ctx_set_doppler = _fwd("fh_ctx_set_doppler")
 fh_gross_histogram = _fwd("fh_gross_histogram")
 fh_clean_gross = _fwd("fh_clean_gross")

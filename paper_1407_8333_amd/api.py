@@ -313,6 +313,11 @@ class Server:
             res.append(d)
         return res
 
+    def drain(self):
+        """Run every queued request to completion (fh_server_drain); the
+        completions are then returned by ``poll``."""
+        check(_lib.fh_server_drain(self.handle))
+
     def cancel(self, rid: int) -> int:
         return _lib.fh_server_cancel(self.handle, ctypes.c_uint64(rid))
 

@@ -1535,19 +1535,27 @@ fh_status fh_server_stats(const fh_server *srv, int32_t *queued, int32_t *runnin
     return FH_OK;
 }
 
-void fh_server_destroy(fh_server *srv) {
-    if (!srv) return;
-    if (srv->ctx) hipSetDevice(srv->ctx->device);
-    // run everything that was accepted, then release
+fh_status fh_server_drain(fh_server *srv) {
+    fh_status s;
+    if (!srv) return fail(FH_E_INVALID, "server is NULL");
+    if ((s = check_ctx(srv->ctx))) return s;
+    // admit and run everything accepted; completions stay for fh_server_poll
     for (;;) {
         retire_lanes(srv);
         admit(srv);
         bool busy = !srv->queue.empty();
         for (const Lane &L : srv->lanes) busy = busy || L.req != 0;
-        if (!busy) break;
+        if (!busy) return FH_OK;
         for (const Lane &L : srv->lanes)
-            if (L.req) hipEventSynchronize(L.ev_done);
+            if (L.req) HIP_OK(hipEventSynchronize(L.ev_done));
     }
+}
+
+void fh_server_destroy(fh_server *srv) {
+    if (!srv) return;
+    if (srv->ctx) hipSetDevice(srv->ctx->device);
+    // run everything that was accepted, then release
+    fh_server_drain(srv);
     for (Lane &L : srv->lanes) {
         if (L.st) hipStreamSynchronize(L.st);
         L.ws.release();

@@ -115,3 +115,29 @@ def test_budget_admission_and_cancel(setup):
     assert done[0]["status"] == 0 and done[1]["status"] == 0
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1])
+
+
+def test_drain_runs_every_queued_request(setup):
+    import torch
+    from paper_1407_8333_amd import api
+    ctx, bands, dpms = setup
+    pm = bands[0]
+    f_lo = pm.k_lo / pm.t_fft + 0.02
+    grid = synth.make_grid(pm, f_lo, f_lo + 0.1, -1e-9, 1e-10)
+    sel = synth.Selection(width=256)
+    skies = [synth.sky_uniform(3, synth.rng_for(40 + k)) for k in range(5)]
+    outs = [torch.empty((3, api.n_subbands(grid, sel), 2, 8), dtype=torch.int32, device="cuda")
+            for _ in range(5)]
+    srv = api.Server(ctx, hbm_budget=1 << 30, lanes=2)
+    for k in range(5):
+        srv.submit(dpms[0], skies[k], grid, sel, outs[k], tag=k)
+    srv.drain()
+    st = srv.stats()
+    assert st["queued"] == 0 and st["running"] == 0 and st["finished"] == 5
+    done = srv.poll()
+    assert sorted(c["tag"] for c in done) == list(range(5)) and all(c["status"] == 0 for c in done)
+    srv.close()
+    for k in range(5):
+        ref = api.fh_hough_candidates(ctx, dpms[0], skies[k], grid, sel)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], ref)
