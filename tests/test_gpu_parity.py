@@ -259,3 +259,32 @@ def test_window_methods_agree(ctx):
     assert torch.equal(outs[0], outs[1])
     assert torch.equal(outs[0], outs[2])
     dpm.release()
+
+
+def test_long_fft_falls_back_to_the_unfused_front(ctx):
+    """An FFT with 7000 peaks does not fit the fused front's LDS (48 KB holds
+    the edges of at most 6128): the library falls back to separate edge and
+    window kernels on 64-bit edges; the map is still bit-exact, weighted and
+    unweighted, and the front serves shorter peakmaps again afterwards."""
+    rng = synth.rng_for(61)
+    t_fft, n = 1024.0, 12
+    k_lo = 300_000
+    pm = synth.random_peakmap(n, t_fft, k_lo, k_lo + 2000, 0.1, rng)
+    dense = np.arange(k_lo, k_lo + 14000, 2, dtype=np.int32)  # 7000 peaks, 2 bins apart
+    segs = [pm.bins[pm.offsets[i]:pm.offsets[i + 1]] for i in range(n)]
+    segs[5] = dense
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in segs])
+    big = synth.Peakmap(t_fft, pm.t, pm.v, off, np.concatenate(segs).astype(np.int32))
+    assert int(np.diff(off).max()) == 7000
+    grid = synth.make_grid(big, (k_lo + 3000) / t_fft, (k_lo + 3400) / t_fft, -3e-8, 2e-9)
+    nhat = synth.sky_uniform(1, rng)[0]
+    got = _gpu_map(ctx, big, grid, nhat)
+    ref = oracle.hough_map(big, grid, nhat)
+    np.testing.assert_array_equal(got, ref.astype(np.int32))
+    wts = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    _assert_weighted_close(_gpu_map(ctx, big, grid, nhat, weights=wts),
+                           oracle.hough_map(big, grid, nhat, weights=wts.astype(np.float64)), wts)
+    small = pm.subset_ffts(range(n))
+    g2 = synth.make_grid(small, (k_lo + 300) / t_fft, (k_lo + 700) / t_fft, -3e-8, 2e-9)
+    np.testing.assert_array_equal(_gpu_map(ctx, small, g2, nhat), oracle.hough_map(small, g2, nhat).astype(np.int32))
