@@ -440,12 +440,14 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // ----------------------------------------------------------------------------
 // tiles
 
-// Window rows ordered for the tiles: each tile wave's run of FFTs sorted by
-// window size, largest first (a counting sort over sizes clipped to 127), so
-// that the four FFTs of a tile block have nearly equal windows.  An entry
-// becomes (lo, local << 16 | count), local = the FFT's place in the run.
-// One workgroup per window row (grid.x = row group * bin blocks, grid.y =
-// slot), one wave per run.
+// Window rows ordered for the tiles.  Tile wave w takes every kTileWaves-th
+// FFT, w, w + 16, w + 32, ... (so that every wave gets FFTs from all over the
+// observation, whose windows widen with |t - t0|); its run of wave_ffts(N)
+// FFTs is sorted by window size, largest first (a counting sort over sizes
+// clipped to 127), so that the four FFTs of a tile block have nearly equal
+// windows.  An entry becomes (lo, m << 16 | count): FFT m * 16 + w of the
+// row.  One workgroup per window row (grid.x = row group * bin blocks,
+// grid.y = slot), one wave per run.
 constexpr int kSortBuckets = 128;
 
 __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, int32_t nrows,
@@ -455,13 +457,13 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per = wave_ffts(n_fft);
     const int64_t row = (int64_t)blockIdx.y * nrows + blockIdx.x;
-    const int2 *src = win + row * win_stride(n_fft) + (int64_t)wave * per;
+    const int2 *src = win + row * win_stride(n_fft) + wave;  // FFT m * kTileWaves + wave at src[m * kTileWaves]
     int2 *dst = wsorted + row * win_stride(n_fft) + (int64_t)wave * per;
     int *h = hist[wave];
     for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
     __syncthreads();
     for (int e = lane; e < per; e += 64) {
-        const int2 w2 = src[e];
+        const int2 w2 = src[(int64_t)e * kTileWaves];
         atomicAdd(&h[kSortBuckets - 1 - min(w2.y - w2.x, kSortBuckets - 1)], 1);
     }
     __syncthreads();
@@ -478,7 +480,7 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     h[2 * lane + 1] = excl + a0;
     __syncthreads();
     for (int e = lane; e < per; e += 64) {
-        const int2 w2 = src[e];
+        const int2 w2 = src[(int64_t)e * kTileWaves];
         const int c = w2.y - w2.x;
         const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
         dst[pos] = make_int2(w2.x, (e << 16) | c);
@@ -717,8 +719,9 @@ __device__ __forceinline__ void tile_output(const TileArgs &A, int slot, int rb,
     }
 }
 
-// The tiles of one workgroup.  Each wave takes a run of wave_ffts(N) FFTs,
-// four at a time (one per lane group; windows past the last FFT are empty).
+// The tiles of one workgroup.  Each wave takes a run of wave_ffts(N) FFTs
+// (every 16th FFT, sorted by window size: see k_sort_windows), four at a time
+// (one per lane group; windows past the last FFT are empty).
 // A block's window data are loaded two blocks ahead and its stripe edges one
 // block ahead (a ring of three blocks), so that the accumulation of a block
 // never waits for memory; the first two blocks of the next tile are loaded
@@ -778,7 +781,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     // are sorted by window size)
     auto stage_y = [&](Quad &Q, const Bufs &B) {
         Q.cnt = Q.pk & 0xFFFF;
-        const uint32_t fc = min((uint32_t)(i_begin + (Q.pk >> 16)), (uint32_t)i_last);
+        const uint32_t fc = min((uint32_t)((Q.pk >> 16) * kTileWaves + wave), (uint32_t)i_last);
         Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
         Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
@@ -833,6 +836,17 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             }
         };
         for (int b = 0; b < nblk; b += 3) {
+            // Issue priority by progress: the SIMD arbiter favours its oldest
+            // wave, which would finish its run well before the youngest while
+            // the rest of the workgroup idles at the barrier; a wave that is
+            // further behind in its (equal) run is served first instead.
+            {
+                const int prog = (b * 20) / nblk;  // 5 % steps of the run
+                if (prog < 10) __builtin_amdgcn_s_setprio(3);
+                else if (prog < 15) __builtin_amdgcn_s_setprio(2);
+                else if (prog < 18) __builtin_amdgcn_s_setprio(1);
+                else __builtin_amdgcn_s_setprio(0);
+            }
             stage_w(qc, b + 2, cur);
             stage_y(qb, cur);
             consume(qa);
@@ -843,6 +857,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             stage_y(qa, cur);
             consume(qc);
         }
+        __builtin_amdgcn_s_setprio(0);
         int tn = -1;
         if (PERSISTENT) {
             if (tid == 0)
