@@ -165,9 +165,9 @@ def serve_bench(ctx, n_req, load, lanes=8, seed=77):
         return dpm, grid, sel, sky
 
     srv = api.Server(ctx, hbm_budget=64 << 30, lanes=lanes)
-    # capacity: a burst of requests submitted at once (64, so that the ramp-down
-    # of the last requests is a small part of the burst)
-    burst = [draw() for _ in range(64)]
+    # capacity: a burst of requests submitted at once (96, so that the ramp-down
+    # of the last requests, when lanes fall idle, is a small part of the burst)
+    burst = [draw() for _ in range(96)]
     outs = [torch.empty((len(b[3]), api.n_subbands(b[1], b[2]), 2, 8), dtype=torch.int32,
                         device="cuda") for b in burst]
     for b, o in zip(burst, outs):  # first use of each shape: tile autotuning, allocation
