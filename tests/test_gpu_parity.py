@@ -288,3 +288,28 @@ def test_long_fft_falls_back_to_the_unfused_front(ctx):
     small = pm.subset_ffts(range(n))
     g2 = synth.make_grid(small, (k_lo + 300) / t_fft, (k_lo + 700) / t_fft, -3e-8, 2e-9)
     np.testing.assert_array_equal(_gpu_map(ctx, small, g2, nhat), oracle.hough_map(small, g2, nhat).astype(np.int32))
+
+
+@pytest.mark.parametrize("n_fft,nf,ns,kf", [(1, 1, 1, 10), (1, 7, 1, 1), (3, 1, 17, 10), (2, 64, 33, 64),
+                                           (40, 2497, 1, 10), (25, 5000, 16, 3)])
+def test_degenerate_grids(ctx, n_fft, nf, ns, kf):
+    """One FFT, one fine bin, one row, row counts just past a tile, a map one
+    bin wider than the widest tile: maps and candidates equal the oracle's."""
+    api = _api()
+    rng = synth.rng_for(7000 + n_fft * 31 + nf + ns + kf)
+    t_fft = 2048.0
+    k_lo = 123_456
+    pm = synth.random_peakmap(n_fft, t_fft, k_lo, k_lo + 800, 0.1, rng)
+    dfd = (1.0 / t_fft) / (max(n_fft, 2) * t_fft * 0.5)
+    grid = synth.Grid(kf=kf, b0=kf * (k_lo + 100), nf=nf, ns=ns, fdot0=-(ns // 2) * dfd, dfdot=dfd,
+                      t0=float(pm.t[0]))
+    nhat = synth.sky_uniform(1, rng)[0]
+    got = _gpu_map(ctx, pm, grid, nhat)
+    ref = oracle.hough_map(pm, grid, nhat)
+    np.testing.assert_array_equal(got, ref.astype(np.int32))
+    sel = synth.Selection(width=max(1, nf // 3))
+    dpm = ctx.upload(pm)
+    dec = api.decode_candidates(api.fh_hough_candidates(ctx, dpm, nhat[None, :], grid, sel))
+    idx, val = oracle.candidates(ref, sel.width, sel.excl, sel.sep)
+    _check_candidates(dec, 0, idx, val, pm.n_fft, sel.theta)
+    dpm.release()
