@@ -68,25 +68,47 @@ KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_
                              "fh_kernels.hip")
 
 
-def committed_traffic(workload, n_sky, tile_bins, weighted):
-    """HBM bytes per tile launch from the committed rocprofv3 byte counters,
-    when they were taken on this workload and on the current kernel source;
-    None otherwise."""
+SQ_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                       "k_tiles_persistent_batch256hz_sq_counters.txt")
+# VALU issue rate of one CU: 4 SIMDs, each retiring one wave64 VALU
+# instruction every 4 clocks, at 2.4 GHz; in wave-instructions per second
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def committed_field(path, key, workload, n_sky, tile_bins, weighted):
+    """A `key = value` figure of a committed rocprofv3 summary, when it was
+    taken on this workload and on the current kernel source; None otherwise."""
     import hashlib
     if not (workload == "batch-256hz" and n_sky == 1024 and tile_bins == 2496 and weighted):
         return None
     try:
         fields = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if " = " in line:
                 k, v = line.split(" = ", 1)
                 fields[k.strip()] = v.strip()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
         if fields.get("kernel_source_sha256") != src:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def committed_traffic(workload, n_sky, tile_bins, weighted):
+    """HBM bytes per tile launch from the committed byte counters."""
+    return committed_field(TRAFFIC_FILE, "traffic_bytes_per_launch", workload, n_sky, tile_bins, weighted)
+
+
+def valu_cobound(achieved, workload, n_sky, tile_bins, weighted):
+    """The tile kernel's VALU co-bound in cell updates/s: the chip's VALU
+    issue rate divided by the VALU instructions per cell update (SQ counters
+    of the same kernel source)."""
+    r = committed_field(SQ_FILE, "valu_instr_per_cell_update", workload, n_sky, tile_bins, weighted)
+    if r is None:
+        return None
+    peak = VALU_WAVE_INSTR_PER_S / r / 1e12
+    return {"peak": peak, "unit": "TOP/s", "frac": achieved / peak, "valu_instr_per_cell_update": r}
 
 
 def pct(xs, q):
@@ -328,6 +350,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": LDS_ATOMIC_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / LDS_ATOMIC_PEAK_TOPS,
                      "traffic": committed_traffic(args.workload, n_sky, plan["tile_bins"], wt is not None),
+                     "valu_cobound": valu_cobound(achieved, args.workload, n_sky, plan["tile_bins"],
+                                                  wt is not None),
                      "kernel": "k_tiles_persistent (one op = one ds_add_u32 cell update)",
                      "launch_ms": tiles_ms_avg, "cells_per_launch": cells_per_launch},
     }
