@@ -496,6 +496,10 @@ __device__ __forceinline__ uint32_t ld_u32(__amdgpu_buffer_rsrc_t r, uint32_t by
     return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
 }
 
+// s_waitcnt operand that waits for every vector-memory access of the wave
+// (vmcnt 0) and leaves the export and LDS/scalar counters alone.
+constexpr int kWaitVmcnt0 = (0x7 << 4) | (0xF << 8);
+
 // Workgroup barrier that orders LDS accesses only: global stores and atomics
 // still in flight are not waited for.
 __device__ __forceinline__ void lds_barrier() {
@@ -719,6 +723,134 @@ __device__ __forceinline__ void tile_output(const TileArgs &A, int slot, int rb,
     }
 }
 
+// Column-maximum output of tile (slot, rb, jb) that also clears the tile for
+// the next one: the output of the candidate search for K_f <= kHold + 1.
+// Phase 1, lane group = segment of columns, lane = row: the window sums H(x)
+// along each row.  The first K_f - 1 columns of a segment are still read by
+// the previous segment, so their sums wait in registers; the later ones are
+// rewritten in place, eight columns per round with every LDS read of a round
+// issued before the first is used.  After a barrier the held sums go back in
+// place, and after another one, phase 2: one thread per column reduces its
+// 16 rows, updates the global maximum and clears the column (dump columns
+// and columns past the map are only cleared).  `mid` runs between the
+// phases (the caller's prefetch of the next tile); the caller's barrier then
+// separates the clearing from the next tile's updates.
+constexpr int kHold = 9;  // held columns per lane: K_f - 1 <= kHold
+
+template <typename Mid>
+__device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb, int jb,
+                                            uint32_t *__restrict__ lds, Mid mid) {
+    constexpr int kB = 8;  // columns per round
+    const int tid = threadIdx.x;
+    const int j = tid & 15;
+    const int W = A.W, kf = A.kf;
+    const int s0 = rb * kTileRows;
+    const int nseg = blockDim.x / kTileRows;
+    const int seg = tid >> 4;
+    const int len = (W + nseg - 1) / nseg;
+    const int64_t bbase = (int64_t)jb * W;
+    const int xend = (int)min((int64_t)W, (int64_t)A.nf - bbase);  // columns of the map
+    const int x0 = seg * len;
+    const int x1 = min(x0 + len, xend);
+    const int nh = max(0, min(kf - 1, x1 - x0));  // held columns [x0, x0 + nh)
+    const bool row_ok = s0 + j < A.ns;
+    uint32_t *__restrict__ P = lds + j;
+    unsigned long long *__restrict__ cm = A.colmax + (int64_t)slot * A.nf + bbase;
+
+    // Phase 1.  Reads past a segment's end are clamped to its last column
+    // (their values are not used); W is a multiple of 64, so a segment starts
+    // at column 63 len <= W even past the map, and no read passes column
+    // W + K_f - 1 (the first dump column).
+    uint32_t acc = 0;
+    if (x0 < x1)
+        for (int c = x0; c < x0 + kf - 1; ++c) acc += P[c * kTileRows];
+    uint32_t hold[kHold];
+    {
+        uint32_t h[kHold], t[kHold];
+#pragma unroll
+        for (int c = 0; c < kHold; ++c) {
+            const int xc = x0 + min(c, max(nh - 1, 0));
+            h[c] = P[(xc + kf - 1) * kTileRows];
+            t[c] = P[xc * kTileRows];
+        }
+#pragma unroll
+        for (int c = 0; c < kHold; ++c) {
+            const uint32_t v = acc + h[c];
+            hold[c] = row_ok ? v : 0u;
+            if (c < nh) acc = v - t[c];
+        }
+    }
+    for (int x = x0 + nh; x < x1; x += kB) {
+        const bool full = x + kB <= x1;
+        uint32_t h[kB], t[kB], o[kB];
+        if (full) {
+            const uint32_t *ph = P + (x + kf - 1) * kTileRows;
+            const uint32_t *pt = P + x * kTileRows;
+#pragma unroll
+            for (int c = 0; c < kB; ++c) {
+                h[c] = ph[c * kTileRows];
+                t[c] = pt[c * kTileRows];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kB; ++c) {
+                const int xc = min(x + c, x1 - 1);
+                h[c] = P[(xc + kf - 1) * kTileRows];
+                t[c] = P[xc * kTileRows];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kB; ++c) {
+            acc += h[c];
+            o[c] = row_ok ? acc : 0u;
+            acc -= t[c];
+        }
+        // a round's writes follow all of its reads: column x + c is read as a
+        // head by earlier rounds only, and as a trail by this round
+#pragma unroll
+        for (int c = 0; c < kB; ++c)
+            if (x + c < x1) P[(x + c) * kTileRows] = o[c];
+    }
+    mid();
+    lds_barrier();
+#pragma unroll
+    for (int c = 0; c < kHold; ++c)
+        if (c < nh) P[(x0 + c) * kTileRows] = hold[c];
+    lds_barrier();
+
+    // Phase 2.  Lane l reads the four 16-byte quarters of its column starting
+    // at quarter (l >> 1) & 3: with columns 64 bytes apart, every eight lanes
+    // then cover the 32 banks once.
+    const int ncols = W + kf - 1 + kDumpCols;
+    const int st = ((tid & 63) >> 1) & 3;
+    int qo[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qo[k] = (k + st) & 3;
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int c = tid; c < ncols; c += blockDim.x) {
+        uint4 *q = reinterpret_cast<uint4 *>(lds + c * kTileRows);
+        if (c < xend) {
+            uint4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = q[qo[k]];
+            uint32_t top = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) top = max(max(top, max(v[k].x, v[k].y)), max(v[k].z, v[k].w));
+            // smallest row holding the maximum (rows past the grid hold 0,
+            // and row 0 always exists, so a row past the grid is never chosen)
+            int r = kTileRows;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int rk = v[k].x == top ? 0 : v[k].y == top ? 1 : v[k].z == top ? 2 : v[k].w == top ? 3 : 4;
+                r = min(r, rk < 4 ? 4 * qo[k] + rk : kTileRows);
+            }
+            atomicMax(cm + c, ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s0 + r)));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[qo[k]] = z;
+    }
+}
+
 // The tiles of one workgroup.  Each wave takes a run of wave_ffts(N) FFTs
 // (every 16th FFT, sorted by window size: see k_sort_windows), four at a time
 // (one per lane group; windows past the last FFT are empty).
@@ -863,6 +995,11 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             if (tid == 0)
                 s_next[(it + 1) & 1] = pos < queue_len(A, home) ? queue_tile(A, home, pos) : steal_tile(A, home);
         }
+        // Drain this wave's vector-memory queue here, where the workgroup
+        // waits anyway: otherwise the compiler cannot tell that the tile
+        // claim above has returned on every path, and the output phase would
+        // open with a full wait that also covers the next tile's prefetch.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         lds_barrier();
         if (PERSISTENT) tn = s_next[(it + 1) & 1];
         Bufs nxt = cur;
@@ -871,12 +1008,23 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             stage_w(qa, 0, nxt);
             stage_w(qb, 1, nxt);
         }
-        tile_output<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        // candidate search: clearing fused into the output, and the next
+        // tile's stripe edges requested while the output still runs
+        const bool fused = COLMAX && !MAP && kf <= kHold + 1;
+        if (fused) {
+            tile_colmax(A, slot, rb, jb, lds, [&] {
+                if (tn >= 0) stage_y(qa, nxt);
+            });
+        } else {
+            tile_output<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
+        }
         if (tn < 0) break;
-        stage_y(qa, nxt);
+        if (!fused) stage_y(qa, nxt);
         lds_barrier();
-        tile_zero(A, lds);
-        lds_barrier();
+        if (!fused) {
+            tile_zero(A, lds);
+            lds_barrier();
+        }
         cur = nxt;
         t = tn;
     }
