@@ -260,18 +260,32 @@ __global__ void __launch_bounds__(256) k_front(
     if (nfl > 0) {
         const int64_t P0 = s_off[0], P1 = s_off[nfl];
         int l = 0;
-        for (int64_t p = P0 + threadIdx.x; p < P1; p += blockDim.x) {
-            while (s_off[l + 1] <= p) ++l;
-            int64_t y;
-            if (shift_mode) {
-                y = (int64_t)kf * (int64_t)bins[p] * kQ + s_c[l];
-            } else {
-                double x = (double)((int64_t)kf * (int64_t)bins[p]) * s_r[l];
-                x = x * kQd;
-                y = (int64_t)floor(x) + s_c[l];
+        // four peaks per thread and round, their natural bins requested
+        // together so that one memory latency covers the round
+        constexpr int kU = 4;
+        for (int64_t pb = P0 + threadIdx.x; pb < P1; pb += kU * (int64_t)blockDim.x) {
+            int32_t kb[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = pb + u * (int64_t)blockDim.x;
+                kb[u] = p < P1 ? bins[p] : 0;
             }
-            Yslot[p + (int64_t)kYPad * (f0 + l)] = (uint32_t)y;  // the tiles use the low word
-            ys[p - P0 + (int64_t)kYPad * l] = y;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = pb + u * (int64_t)blockDim.x;
+                if (p >= P1) break;
+                while (s_off[l + 1] <= p) ++l;
+                int64_t y;
+                if (shift_mode) {
+                    y = (int64_t)kf * (int64_t)kb[u] * kQ + s_c[l];
+                } else {
+                    double x = (double)((int64_t)kf * (int64_t)kb[u]) * s_r[l];
+                    x = x * kQd;
+                    y = (int64_t)floor(x) + s_c[l];
+                }
+                Yslot[p + (int64_t)kYPad * (f0 + l)] = (uint32_t)y;  // the tiles use the low word
+                ys[p - P0 + (int64_t)kYPad * l] = y;
+            }
         }
         for (int t = threadIdx.x; t < nfl * kYPad; t += blockDim.x) {
             const int fl = t / kYPad;
@@ -462,9 +476,18 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     int *h = hist[wave];
     for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
     __syncthreads();
-    for (int e = lane; e < per; e += 64) {
-        const int2 w2 = src[(int64_t)e * kTileWaves];
-        atomicAdd(&h[kSortBuckets - 1 - min(w2.y - w2.x, kSortBuckets - 1)], 1);
+    // entries are read four per lane and round (one memory latency per round)
+    constexpr int kU = 4;
+    for (int e0 = lane; e0 < per; e0 += kU * 64) {
+        int2 w2[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + 64 * u;
+            w2[u] = e < per ? src[(int64_t)e * kTileWaves] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (e0 + 64 * u < per) atomicAdd(&h[kSortBuckets - 1 - min(w2[u].y - w2[u].x, kSortBuckets - 1)], 1);
     }
     __syncthreads();
     // exclusive prefix sum over the buckets (lane L holds buckets 2L, 2L+1)
@@ -479,11 +502,21 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     h[2 * lane] = excl;
     h[2 * lane + 1] = excl + a0;
     __syncthreads();
-    for (int e = lane; e < per; e += 64) {
-        const int2 w2 = src[(int64_t)e * kTileWaves];
-        const int c = w2.y - w2.x;
-        const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
-        dst[pos] = make_int2(w2.x, (e << 16) | c);
+    for (int e0 = lane; e0 < per; e0 += kU * 64) {
+        int2 w2[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + 64 * u;
+            w2[u] = e < per ? src[(int64_t)e * kTileWaves] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + 64 * u;
+            if (e >= per) break;
+            const int c = w2[u].y - w2[u].x;
+            const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
+            dst[pos] = make_int2(w2[u].x, (e << 16) | c);
+        }
     }
 }
 
