@@ -463,16 +463,28 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // row.  One workgroup per window row (grid.x = row group * bin blocks,
 // grid.y = slot), one wave per run.
 constexpr int kSortBuckets = 128;
+// rows of at most this many bytes are first copied into LDS with 16-byte
+// loads (the runs read the row with a 128-byte stride, twice)
+constexpr int kSortStageBytes = 128 * 1024;
 
+template <bool STAGED>
 __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, int32_t nrows,
                                                                const int2 *__restrict__ win,
                                                                int2 *__restrict__ wsorted) {
+    extern __shared__ int4 s_row4[];
     __shared__ int hist[kTileWaves][kSortBuckets];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per = wave_ffts(n_fft);
+    const int n_pad = win_stride(n_fft);  // a multiple of 64 entries
     const int64_t row = (int64_t)blockIdx.y * nrows + blockIdx.x;
-    const int2 *src = win + row * win_stride(n_fft) + wave;  // FFT m * kTileWaves + wave at src[m * kTileWaves]
-    int2 *dst = wsorted + row * win_stride(n_fft) + (int64_t)wave * per;
+    const int2 *rowp = win + row * n_pad;
+    if (STAGED) {
+        const int4 *g4 = reinterpret_cast<const int4 *>(rowp);
+        for (int i = threadIdx.x; i < n_pad / 2; i += blockDim.x) s_row4[i] = g4[i];
+    }
+    // FFT m * kTileWaves + wave of the row is entry m of this wave's run
+    const int2 *src = (STAGED ? reinterpret_cast<const int2 *>(s_row4) : rowp) + wave;
+    int2 *dst = wsorted + row * n_pad + (int64_t)wave * per;
     int *h = hist[wave];
     for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
     __syncthreads();
@@ -1365,7 +1377,11 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
 hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t n_slots, const int2 *win,
                                int2 *wsorted, hipStream_t st) {
     dim3 grid(nrbg * nbb, n_slots);
-    k_sort_windows<<<grid, kTileThreads, 0, st>>>(n_fft, nrbg * nbb, win, wsorted);
+    const size_t row_bytes = (size_t)win_stride(n_fft) * sizeof(int2);
+    if (row_bytes <= (size_t)kSortStageBytes)
+        k_sort_windows<true><<<grid, kTileThreads, row_bytes, st>>>(n_fft, nrbg * nbb, win, wsorted);
+    else
+        k_sort_windows<false><<<grid, kTileThreads, 0, st>>>(n_fft, nrbg * nbb, win, wsorted);
     return hipGetLastError();
 }
 
@@ -1410,7 +1426,9 @@ hipError_t init_kernel_attributes() {
     if ((e = set_tile_attrs<true, false, true>()) != hipSuccess) return e;
     if ((e = set_tile_attrs<false, true, true>()) != hipSuccess) return e;
     if ((e = set_tile_attrs<false, true, false>()) != hipSuccess) return e;
-    return set_tile_attrs<false, false, true>();
+    if ((e = set_tile_attrs<false, false, true>()) != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_sort_windows<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kSortStageBytes);
 }
 
 hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
