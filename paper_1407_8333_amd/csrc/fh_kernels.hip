@@ -617,6 +617,7 @@ __device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t,
 // (g, j) holds its group's window, row term -j dG and weight, and the stripe
 // edges of its peaks in up to two chunks of 16.
 struct Quad {
+    int g, run;          // block id claimed from the tile's counter; its run g % 16
     int lo, pk;          // window start; FFT place in the run << 16 | peak count
     int32_t dg;          // row step dG of the group's FFT
     uint32_t t, wq;      // row term -j dG (mod 2^32); fixed-point weight
@@ -907,10 +908,10 @@ __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb,
 // XCD queues until all are exhausted; otherwise the workgroup runs tile
 // tile_base + blockIdx.x only.
 template <bool WEIGHTED, bool MAP, bool COLMAX, bool PERSISTENT>
-__device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restrict__ lds, int *s_next) {
+__device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restrict__ lds, int *s_next,
+                                          int *s_cnt) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = lane & 15;
     const int grp = lane >> 4;
     const int W = A.W, kf = A.kf;
@@ -923,8 +924,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     const uint32_t mtab = chunk_pattern(lane);       // lane n holds m(n), n <= 16
     const int32_t n_pad = win_stride(A.n_fft);
     const int per = wave_ffts(A.n_fft);
-    const int i_begin = wave * per;
     const int nblk = per >> 2;
+    const int total = kTileWaves * nblk;  // blocks of a tile
     const int i_last = A.n_fft - 1;
     const int home = blockIdx.x % kXcds;
     const __amdgpu_buffer_rsrc_t r_t = buf(A.rowt), r_dg = buf(A.dg);
@@ -944,12 +945,25 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.dg);
         return b;
     };
-    // window data of block bb (stage 1).  The ring prefetches two blocks past
-    // the wave's last one (never consumed); those reads stay inside the
-    // window row.
-    auto stage_w = [&](Quad &Q, int bb, const Bufs &B) {
-        const uint32_t e = (uint32_t)(i_begin + 4 * bb + grp);
-        const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(B.win, min(e, (uint32_t)(n_pad - 1)) * 8u, 0, 0);
+    // Blocks are handed out dynamically: block g of a tile is block g / 16 of
+    // run g % 16 (four consecutive entries of that run), so the counter walks
+    // the runs' largest windows first, and a wave that the SIMD arbiter
+    // serves less simply takes fewer blocks.  `claim` returns the counter's
+    // old value in lane 0; it is read (and waited for) only when the block is
+    // staged, one block later.
+    auto claim = [&](int par) {
+        int g = 0;
+        if (lane == 0) g = atomicAdd(s_cnt + par, 1);
+        return g;
+    };
+    // window data of block g (stage 1).  Blocks past the last one (claims
+    // after the counter ran out) read the row's last entry, an empty window.
+    auto stage_w = [&](Quad &Q, int gv, const Bufs &B) {
+        Q.g = __builtin_amdgcn_readfirstlane(gv);
+        Q.run = Q.g & (kTileWaves - 1);
+        const uint32_t e = (uint32_t)(Q.run * per + 4 * (Q.g >> 4) + grp);
+        const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(
+            B.win, (Q.g < total ? e : (uint32_t)(n_pad - 1)) * 8u, 0, 0);
         Q.lo = (int)w2[0];
         Q.pk = (int)w2[1];
     };
@@ -958,7 +972,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     // are sorted by window size)
     auto stage_y = [&](Quad &Q, const Bufs &B) {
         Q.cnt = Q.pk & 0xFFFF;
-        const uint32_t fc = min((uint32_t)((Q.pk >> 16) * kTileWaves + wave), (uint32_t)i_last);
+        const uint32_t fc = min((uint32_t)((Q.pk >> 16) * kTileWaves + Q.run), (uint32_t)i_last);
         Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
         Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
@@ -977,18 +991,23 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     if (PERSISTENT) {
         if (tid == 0) s_next[0] = steal_tile(A, home);
     }
+    if (tid < 2) s_cnt[tid] = 0;
     tile_zero(A, lds);
     lds_barrier();
     t = PERSISTENT ? s_next[0] : A.tile_base + (int)blockIdx.x;
     if (t < 0 || nblk == 0) return;  // nblk > 0 whenever there is an FFT
     Quad qa, qb, qc;
     Bufs cur = tile_bufs(t);
-    stage_w(qa, 0, cur);
-    stage_w(qb, 1, cur);
+    stage_w(qa, claim(0), cur);
+    stage_w(qb, claim(0), cur);
     stage_y(qa, cur);
     for (int it = 0;; ++it) {
+        const int par = it & 1;  // block counter of this tile; the other is the next tile's
         int pos = 0;
         if (PERSISTENT && tid == 0) pos = atomicAdd(A.queue_ctr + home, 1);
+        // the next tile's counter was last used by the previous tile, whose
+        // claims all came before the barrier that ended its accumulation
+        if (tid == 0) s_cnt[par ^ 1] = 0;
         int slot, rb, jb;
         decode_tile(A, t, slot, rb, jb);
         const int s0 = rb * kTileRows;
@@ -1012,29 +1031,28 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
                 stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
             }
         };
-        for (int b = 0; b < nblk; b += 3) {
-            // Issue priority by progress: the SIMD arbiter favours its oldest
-            // wave, which would finish its run well before the youngest while
-            // the rest of the workgroup idles at the barrier; a wave that is
-            // further behind in its (equal) run is served first instead.
-            {
-                const int prog = (b * 20) / nblk;  // 5 % steps of the run
-                if (prog < 10) __builtin_amdgcn_s_setprio(3);
-                else if (prog < 15) __builtin_amdgcn_s_setprio(2);
-                else if (prog < 18) __builtin_amdgcn_s_setprio(1);
-                else __builtin_amdgcn_s_setprio(0);
-            }
-            stage_w(qc, b + 2, cur);
+        // Ring of three blocks: a block's window is loaded two blocks ahead,
+        // its stripe edges one block ahead, its claim three blocks ahead.
+        // Claims are handed out in order, so once one block is past the end,
+        // so are the blocks staged after it.
+        int gn = claim(par);
+        for (;;) {
+            stage_w(qc, gn, cur);
+            gn = claim(par);
             stage_y(qb, cur);
+            if (qa.g >= total) break;
             consume(qa);
-            stage_w(qa, b + 3, cur);
+            stage_w(qa, gn, cur);
+            gn = claim(par);
             stage_y(qc, cur);
+            if (qb.g >= total) break;
             consume(qb);
-            stage_w(qb, b + 4, cur);
+            stage_w(qb, gn, cur);
+            gn = claim(par);
             stage_y(qa, cur);
+            if (qc.g >= total) break;
             consume(qc);
         }
-        __builtin_amdgcn_s_setprio(0);
         int tn = -1;
         if (PERSISTENT) {
             if (tid == 0)
@@ -1050,8 +1068,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         Bufs nxt = cur;
         if (tn >= 0) {
             nxt = tile_bufs(tn);
-            stage_w(qa, 0, nxt);
-            stage_w(qb, 1, nxt);
+            stage_w(qa, claim(par ^ 1), nxt);
+            stage_w(qb, claim(par ^ 1), nxt);
         }
         // candidate search: clearing fused into the output, and the next
         // tile's stripe edges requested while the output still runs
@@ -1078,7 +1096,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
 template <bool WEIGHTED, bool MAP, bool COLMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
     extern __shared__ uint32_t lds[];
-    run_tiles<WEIGHTED, MAP, COLMAX, false>(A, lds, nullptr);
+    __shared__ int s_cnt[2];
+    run_tiles<WEIGHTED, MAP, COLMAX, false>(A, lds, nullptr, s_cnt);
 }
 
 // One workgroup per CU.  The next tile of the home queue is claimed when a
@@ -1089,7 +1108,8 @@ template <bool WEIGHTED, bool MAP, bool COLMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ int s_next[2];
-    run_tiles<WEIGHTED, MAP, COLMAX, true>(A, lds, s_next);
+    __shared__ int s_cnt[2];
+    run_tiles<WEIGHTED, MAP, COLMAX, true>(A, lds, s_next, s_cnt);
 }
 
 // ----------------------------------------------------------------------------
