@@ -948,12 +948,12 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     // Blocks are handed out dynamically: block g of a tile is block g / 16 of
     // run g % 16 (four consecutive entries of that run), so the counter walks
     // the runs' largest windows first, and a wave that the SIMD arbiter
-    // serves less simply takes fewer blocks.  `claim` returns the counter's
-    // old value in lane 0; it is read (and waited for) only when the block is
-    // staged, one block later.
-    auto claim = [&](int par) {
+    // serves less simply takes fewer blocks.  `claim` takes n blocks and
+    // returns the first in lane 0; it is read (and waited for) only when the
+    // blocks are staged.
+    auto claim = [&](int par, int n) {
         int g = 0;
-        if (lane == 0) g = atomicAdd(s_cnt + par, 1);
+        if (lane == 0) g = atomicAdd(s_cnt + par, n);
         return g;
     };
     // window data of block g (stage 1).  Blocks past the last one (claims
@@ -998,8 +998,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     if (t < 0 || nblk == 0) return;  // nblk > 0 whenever there is an FFT
     Quad qa, qb, qc;
     Bufs cur = tile_bufs(t);
-    stage_w(qa, claim(0), cur);
-    stage_w(qb, claim(0), cur);
+    stage_w(qa, claim(0, 1), cur);
+    stage_w(qb, claim(0, 1), cur);
     stage_y(qa, cur);
     for (int it = 0;; ++it) {
         const int par = it & 1;  // block counter of this tile; the other is the next tile's
@@ -1032,23 +1032,23 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             }
         };
         // Ring of three blocks: a block's window is loaded two blocks ahead,
-        // its stripe edges one block ahead, its claim three blocks ahead.
-        // Claims are handed out in order, so once one block is past the end,
-        // so are the blocks staged after it.
-        int gn = claim(par);
+        // its stripe edges one block ahead.  Blocks are claimed three at a
+        // time, one round ahead, so a wave drains its LDS queue to read a
+        // claim once per three blocks.  A wave's claims grow, so once one
+        // block is past the end, so are the blocks staged after it.
+        int gv = claim(par, 3);
         for (;;) {
-            stage_w(qc, gn, cur);
-            gn = claim(par);
+            const int g3 = __builtin_amdgcn_readfirstlane(gv);
+            gv = claim(par, 3);
+            stage_w(qc, g3, cur);
             stage_y(qb, cur);
             if (qa.g >= total) break;
             consume(qa);
-            stage_w(qa, gn, cur);
-            gn = claim(par);
+            stage_w(qa, g3 + 1, cur);
             stage_y(qc, cur);
             if (qb.g >= total) break;
             consume(qb);
-            stage_w(qb, gn, cur);
-            gn = claim(par);
+            stage_w(qb, g3 + 2, cur);
             stage_y(qa, cur);
             if (qc.g >= total) break;
             consume(qc);
@@ -1068,8 +1068,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         Bufs nxt = cur;
         if (tn >= 0) {
             nxt = tile_bufs(tn);
-            stage_w(qa, claim(par ^ 1), nxt);
-            stage_w(qb, claim(par ^ 1), nxt);
+            stage_w(qa, claim(par ^ 1, 1), nxt);
+            stage_w(qb, claim(par ^ 1, 1), nxt);
         }
         // candidate search: clearing fused into the output, and the next
         // tile's stripe edges requested while the output still runs
