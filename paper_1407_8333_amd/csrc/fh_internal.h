@@ -87,10 +87,11 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
                        int32_t shift_mode, double q, hipStream_t st);
 // fused stripe edges + weights + windows (LDS-staged edges of F FFTs per
 // workgroup); F = front_ffts_per_block(max peaks of one FFT), 0 when even one
-// FFT's edges do not fit (then use launch_prep + launch_windows).  At most
-// 24 KB per workgroup keeps six or more workgroups on a CU to hide the
-// latency of the bins loads and the window searches.
-constexpr int kFrontLdsBytes = 24 * 1024;
+// FFT's edges do not fit (then use launch_prep + launch_windows).  FFTs of
+// kFrontBigFft peaks or more go at most four to a workgroup: the front is
+// latency-bound, and more, smaller workgroups per CU hide more of it.
+constexpr int kFrontLdsBytes = 48 * 1024;
+constexpr int kFrontBigFft = 256;
 constexpr int kFrontMaxF = 16;
 int front_ffts_per_block(int32_t max_per_fft);
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,

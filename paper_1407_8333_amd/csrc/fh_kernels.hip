@@ -1373,7 +1373,7 @@ hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, c
 }
 
 int front_ffts_per_block(int32_t max_per_fft) {
-    for (int F = kFrontMaxF; F >= 1; F >>= 1)
+    for (int F = max_per_fft >= kFrontBigFft ? 4 : kFrontMaxF; F >= 1; F >>= 1)
         if ((int64_t)F * (max_per_fft + kYPad) * 8 <= kFrontLdsBytes) return F;
     return 0;
 }
