@@ -454,14 +454,14 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // ----------------------------------------------------------------------------
 // tiles
 
-// Window rows ordered for the tiles.  Tile wave w takes every kTileWaves-th
-// FFT, w, w + 16, w + 32, ... (so that every wave gets FFTs from all over the
-// observation, whose windows widen with |t - t0|); its run of wave_ffts(N)
-// FFTs is sorted by window size, largest first (a counting sort over sizes
-// clipped to 127), so that the four FFTs of a tile block have nearly equal
-// windows.  An entry becomes (lo, m << 16 | count): FFT m * 16 + w of the
-// row.  One workgroup per window row (grid.x = row group * bin blocks,
-// grid.y = slot), one wave per run.
+// Window rows ordered for the tiles.  Run w of a row holds every
+// kTileWaves-th FFT, w, w + 16, w + 32, ... (so that every run spans the
+// whole observation, whose windows widen with |t - t0|); its wave_ffts(N)
+// FFTs are sorted by window size, largest first (a counting sort over sizes
+// clipped to 127), so that the four FFTs of a tile block (four consecutive
+// entries of a run) have nearly equal windows.  An entry becomes
+// (lo, m << 16 | count): FFT m * 16 + w of the row.  One workgroup per window
+// row (grid.x = row group * bin blocks, grid.y = slot), one wave per run.
 constexpr int kSortBuckets = 128;
 // rows of at most this many bytes are first copied into LDS with 16-byte
 // loads (the runs read the row with a 128-byte stride, twice)
@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
         const int4 *g4 = reinterpret_cast<const int4 *>(rowp);
         for (int i = threadIdx.x; i < n_pad / 2; i += blockDim.x) s_row4[i] = g4[i];
     }
-    // FFT m * kTileWaves + wave of the row is entry m of this wave's run
+    // FFT m * kTileWaves + wave of the row is entry m of run `wave`
     const int2 *src = (STAGED ? reinterpret_cast<const int2 *>(s_row4) : rowp) + wave;
     int2 *dst = wsorted + row * n_pad + (int64_t)wave * per;
     int *h = hist[wave];
@@ -613,15 +613,15 @@ __device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t,
     if (m & 0x8000u) stripe_run<15, 16>(v, t, dump, lane_off, val, lds);
 }
 
-// One block: four FFTs of a wave's run, FFT 4 b + g in lane group g.  Lane
-// (g, j) holds its group's window, row term -j dG and weight, and the stripe
-// edges of its peaks in up to two chunks of 16.
+// One block: four consecutive FFTs of a sorted run, entry 4 b + g in lane
+// group g.  Lane (g, j) holds its group's window, row term -j dG and weight,
+// and the stripe edges of its peaks in up to two chunks of 16.
 struct Quad {
     int g, run;          // block id claimed from the tile's counter; its run g % 16
     int lo, pk;          // window start; FFT place in the run << 16 | peak count
     int32_t dg;          // row step dG of the group's FFT
     uint32_t t, wq;      // row term -j dG (mod 2^32); fixed-point weight
-    int cnt;             // peaks in the window (0 past the wave's run)
+    int cnt;             // peaks in the window (0 past the tile's blocks)
     int32_t q1, q2;      // chunk positions of the lane's peaks
     uint32_t y0, y1;     // low words of their stripe edges
     uint32_t m1, m2;     // lane patterns of the two chunks
@@ -897,9 +897,9 @@ __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb,
     }
 }
 
-// The tiles of one workgroup.  Each wave takes a run of wave_ffts(N) FFTs
-// (every 16th FFT, sorted by window size: see k_sort_windows), four at a time
-// (one per lane group; windows past the last FFT are empty).
+// The tiles of one workgroup.  The waves take the tile's blocks (four FFTs
+// of a sorted run, one per lane group; windows past the last FFT are empty)
+// from a counter in LDS, so that each wave takes as many as it can process.
 // A block's window data are loaded two blocks ahead and its stripe edges one
 // block ahead (a ring of three blocks), so that the accumulation of a block
 // never waits for memory; the first two blocks of the next tile are loaded
