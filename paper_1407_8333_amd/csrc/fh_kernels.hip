@@ -467,7 +467,6 @@ constexpr int kSortBuckets = 128;
 // loads (the runs read the row with a 128-byte stride, twice)
 constexpr int kSortStageBytes = 128 * 1024;
 
-template <bool STAGED>
 __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, int32_t nrows,
                                                                const int2 *__restrict__ win,
                                                                int2 *__restrict__ wsorted) {
@@ -478,12 +477,12 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
     const int n_pad = win_stride(n_fft);  // a multiple of 64 entries
     const int64_t row = (int64_t)blockIdx.y * nrows + blockIdx.x;
     const int2 *rowp = win + row * n_pad;
-    if (STAGED) {
+    {
         const int4 *g4 = reinterpret_cast<const int4 *>(rowp);
         for (int i = threadIdx.x; i < n_pad / 2; i += blockDim.x) s_row4[i] = g4[i];
     }
     // FFT m * kTileWaves + wave of the row is entry m of run `wave`
-    const int2 *src = (STAGED ? reinterpret_cast<const int2 *>(s_row4) : rowp) + wave;
+    const int2 *src = reinterpret_cast<const int2 *>(s_row4) + wave;
     int2 *dst = wsorted + row * n_pad + (int64_t)wave * per;
     int *h = hist[wave];
     for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
@@ -528,6 +527,91 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
             const int c = w2[u].y - w2[u].x;
             const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
             dst[pos] = make_int2(w2[u].x, (e << 16) | c);
+        }
+    }
+}
+
+// Rows longer than kSortStageEntries entries: the same sort, the row copied
+// into LDS in pieces of kSortStageEntries (128 KB), once per pass.
+constexpr int kSortStageEntries = 16384;
+
+__global__ void __launch_bounds__(kTileThreads) k_sort_windows_long(int32_t n_fft, int32_t nrows,
+                                                               const int2 *__restrict__ win,
+                                                               int2 *__restrict__ wsorted) {
+    extern __shared__ int4 s_row4[];
+    __shared__ int hist[kTileWaves][kSortBuckets];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = wave_ffts(n_fft);
+    const int n_pad = win_stride(n_fft);  // a multiple of 64 entries
+    const int piece = kSortStageEntries;
+    const int64_t row = (int64_t)blockIdx.y * nrows + blockIdx.x;
+    const int2 *rowp = win + row * n_pad;
+    const int2 *s_row = reinterpret_cast<const int2 *>(s_row4);
+    int2 *dst = wsorted + row * n_pad + (int64_t)wave * per;
+    int *h = hist[wave];
+    // entries [p0, p0 + piece) of the row into LDS (both multiples of 64)
+    auto stage = [&](int p0) {
+        const int n = min(piece, n_pad - p0);
+        const int4 *g4 = reinterpret_cast<const int4 *>(rowp + p0);
+        for (int i = threadIdx.x; i < n / 2; i += blockDim.x) s_row4[i] = g4[i];
+    };
+    for (int b = lane; b < kSortBuckets; b += 64) h[b] = 0;
+    __syncthreads();
+    // Entry e of run `wave` is row entry e * kTileWaves + wave; a piece
+    // starting at p0 holds the run's entries [p0 / 16, (p0 + piece) / 16).
+    // Entries are read four per lane and round.
+    constexpr int kU = 4;
+    for (int p0 = 0; p0 < n_pad; p0 += piece) {
+        if (p0 > 0) __syncthreads();
+        stage(p0);
+        __syncthreads();
+        const int e_lo = p0 / kTileWaves, e_hi = min(per, (p0 + piece) / kTileWaves);
+        for (int e0 = e_lo + lane; e0 < e_hi; e0 += kU * 64) {
+            int2 w2[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + 64 * u;
+                w2[u] = e < e_hi ? s_row[(e - e_lo) * kTileWaves + wave] : make_int2(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (e0 + 64 * u < e_hi)
+                    atomicAdd(&h[kSortBuckets - 1 - min(w2[u].y - w2[u].x, kSortBuckets - 1)], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive prefix sum over the buckets (lane L holds buckets 2L, 2L+1)
+    const int a0 = h[2 * lane], a1 = h[2 * lane + 1];
+    int incl = a0 + a1;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int excl = incl - (a0 + a1);
+    __syncthreads();
+    h[2 * lane] = excl;
+    h[2 * lane + 1] = excl + a0;
+    __syncthreads();
+    for (int p0 = 0; p0 < n_pad; p0 += piece) {
+        if (p0 > 0) __syncthreads();
+        stage(p0);
+        __syncthreads();
+        const int e_lo = p0 / kTileWaves, e_hi = min(per, (p0 + piece) / kTileWaves);
+        for (int e0 = e_lo + lane; e0 < e_hi; e0 += kU * 64) {
+            int2 w2[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + 64 * u;
+                w2[u] = e < e_hi ? s_row[(e - e_lo) * kTileWaves + wave] : make_int2(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + 64 * u;
+                if (e >= e_hi) break;
+                const int c = w2[u].y - w2[u].x;
+                const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
+                dst[pos] = make_int2(w2[u].x, (e << 16) | c);
+            }
         }
     }
 }
@@ -1399,9 +1483,10 @@ hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t
     dim3 grid(nrbg * nbb, n_slots);
     const size_t row_bytes = (size_t)win_stride(n_fft) * sizeof(int2);
     if (row_bytes <= (size_t)kSortStageBytes)
-        k_sort_windows<true><<<grid, kTileThreads, row_bytes, st>>>(n_fft, nrbg * nbb, win, wsorted);
+        k_sort_windows<<<grid, kTileThreads, row_bytes, st>>>(n_fft, nrbg * nbb, win, wsorted);
     else
-        k_sort_windows<false><<<grid, kTileThreads, 0, st>>>(n_fft, nrbg * nbb, win, wsorted);
+        k_sort_windows_long<<<grid, kTileThreads, (size_t)kSortStageEntries * sizeof(int2), st>>>(
+            n_fft, nrbg * nbb, win, wsorted);
     return hipGetLastError();
 }
 
@@ -1447,8 +1532,11 @@ hipError_t init_kernel_attributes() {
     if ((e = set_tile_attrs<false, true, true>()) != hipSuccess) return e;
     if ((e = set_tile_attrs<false, true, false>()) != hipSuccess) return e;
     if ((e = set_tile_attrs<false, false, true>()) != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_sort_windows<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kSortStageBytes);
+    if ((e = hipFuncSetAttribute((const void *)k_sort_windows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kSortStageBytes)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_sort_windows_long, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kSortStageEntries * (int)sizeof(int2));
 }
 
 hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
