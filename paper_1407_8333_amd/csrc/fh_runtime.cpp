@@ -50,7 +50,7 @@ struct DevBuf {
         if (ptr) {
             hipError_t e = hipStreamSynchronize(st);
             if (e != hipSuccess) return fail(FH_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
-            hipFree(ptr);
+            (void)hipFree(ptr);
             ptr = nullptr;
             bytes = 0;
         }
@@ -63,7 +63,7 @@ struct DevBuf {
         return FH_OK;
     }
     void release() {
-        if (ptr) hipFree(ptr);
+        if (ptr) (void)hipFree(ptr);
         ptr = nullptr;
         bytes = 0;
     }
@@ -77,7 +77,7 @@ struct PinnedBuf {
         if (ptr) {
             hipError_t e = hipStreamSynchronize(st);
             if (e != hipSuccess) return fail(FH_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
-            hipHostFree(ptr);
+            (void)hipHostFree(ptr);
             ptr = nullptr;
         }
         size_t n = std::max(want, (size_t)4096);
@@ -90,7 +90,7 @@ struct PinnedBuf {
         return FH_OK;
     }
     void release() {
-        if (ptr) hipHostFree(ptr);
+        if (ptr) (void)hipHostFree(ptr);
         ptr = nullptr;
         bytes = 0;
     }
@@ -262,6 +262,8 @@ hipEvent_t next_event(fh_ctx *ctx) {
 }
 
 // Records an event before a group of launches and another after it.
+// Profiling span.  A record that fails leaves an unrecorded event, which
+// fh_ctx_profile_read then reports through hipEventElapsedTime.
 struct Timed {
     fh_ctx *ctx;
     hipStream_t st;
@@ -270,14 +272,14 @@ struct Timed {
     Timed(fh_ctx *c, hipStream_t s, int k) : ctx(c), st(s), kind(k) {
         if (ctx->profiling) {
             a = next_event(ctx);
-            if (a) hipEventRecord(a, st);
+            if (a) (void)hipEventRecord(a, st);
         }
     }
     ~Timed() {
         if (a) {
             hipEvent_t b = next_event(ctx);
             if (b) {
-                hipEventRecord(b, st);
+                (void)hipEventRecord(b, st);
                 ctx->spans.push_back({a, b, kind});
             }
         }
@@ -531,8 +533,8 @@ fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sk
             best_w = w;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ctx->profiling = was;
     if (s) return s;
     ctx->tuned[tune_key(pm, g, weighted)] = best_w;
@@ -642,11 +644,11 @@ fh_status fh_ctx_create(int32_t device, fh_ctx **out) {
 
 void fh_ctx_destroy(fh_ctx *ctx) {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
     for (auto &e : ctx->graphs) {
-        hipGraphExecDestroy(e.exec);
-        hipGraphDestroy(e.graph);
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
     }
     ctx->graphs.clear();
     ctx->main_ws.release();
@@ -654,7 +656,7 @@ void fh_ctx_destroy(fh_ctx *ctx) {
     for (DevBuf *b : {&ctx->rf_offsets, &ctx->rf_bins, &ctx->rf_t, &ctx->rf_v, &ctx->rf_first, &ctx->rf_counts,
                       &ctx->rf_cands, &ctx->rf_aux, &ctx->cl_hist, &ctx->cl_s2, &ctx->cl_out})
         b->release();
-    for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -805,8 +807,8 @@ fh_status fh_peakmap_from_spectra(fh_ctx *ctx, int32_t n_fft, int32_t n_bins, in
     if (hipMalloc(&scratch, 4 * (size_t)n_fft * cap) != hipSuccess || hipMalloc(&counts, 4 * (size_t)n_fft) != hipSuccess ||
         hipMalloc(&pm->d_offsets, b_off) != hipSuccess || hipMalloc(&pm->d_t, b_t) != hipSuccess ||
         hipMalloc(&pm->d_v, b_v) != hipSuccess) {
-        if (scratch) hipFree(scratch);
-        if (counts) hipFree(counts);
+        if (scratch) (void)hipFree(scratch);
+        if (counts) (void)hipFree(counts);
         fh_peakmap_release(ctx, pm);
         return fail(FH_E_NOMEM, "device allocation for the peakmap failed");
     }
@@ -822,8 +824,8 @@ fh_status fh_peakmap_from_spectra(fh_ctx *ctx, int32_t n_fft, int32_t n_bins, in
     if (e == hipSuccess) e = hipMemcpyAsync(pm->d_t, t, b_t, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pm->d_v, v, b_v, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(scratch);
-    hipFree(counts);
+    (void)hipFree(scratch);
+    (void)hipFree(counts);
     if (e != hipSuccess) {
         fh_peakmap_release(ctx, pm);
         return fail(e == hipErrorOutOfMemory ? FH_E_NOMEM : FH_E_DEVICE, "peakmap construction failed: %s",
@@ -859,11 +861,11 @@ fh_status fh_peakmap_shape(const fh_peakmap *pm, int32_t *n_fft, int64_t *n_peak
 
 void fh_peakmap_release(fh_ctx *ctx, fh_peakmap *pm) {
     if (!pm) return;
-    if (ctx) hipSetDevice(ctx->device);
-    if (pm->d_offsets) hipFree(pm->d_offsets);
-    if (pm->d_bins) hipFree(pm->d_bins);
-    if (pm->d_t) hipFree(pm->d_t);
-    if (pm->d_v) hipFree(pm->d_v);
+    if (ctx) (void)hipSetDevice(ctx->device);
+    if (pm->d_offsets) (void)hipFree(pm->d_offsets);
+    if (pm->d_bins) (void)hipFree(pm->d_bins);
+    if (pm->d_t) (void)hipFree(pm->d_t);
+    if (pm->d_v) (void)hipFree(pm->d_v);
     delete pm;
 }
 
@@ -1233,19 +1235,19 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         hipError_t e = hipStreamEndCapture(st, &graph);
         ctx->profiling = was;
         if (s) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return s;
         }
         if (e != hipSuccess) return fail(FH_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return fail(FH_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
         }
         if (ctx->graphs.size() >= 16) {
-            hipGraphExecDestroy(ctx->graphs.front().exec);
-            hipGraphDestroy(ctx->graphs.front().graph);
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            (void)hipGraphDestroy(ctx->graphs.front().graph);
             ctx->graphs.erase(ctx->graphs.begin());
         }
         ctx->graphs.push_back({key, graph, exec});
@@ -1553,15 +1555,15 @@ fh_status fh_server_drain(fh_server *srv) {
 
 void fh_server_destroy(fh_server *srv) {
     if (!srv) return;
-    if (srv->ctx) hipSetDevice(srv->ctx->device);
+    if (srv->ctx) (void)hipSetDevice(srv->ctx->device);
     // run everything that was accepted, then release
     fh_server_drain(srv);
     for (Lane &L : srv->lanes) {
-        if (L.st) hipStreamSynchronize(L.st);
+        if (L.st) (void)hipStreamSynchronize(L.st);
         L.ws.release();
-        if (L.ev_start) hipEventDestroy(L.ev_start);
-        if (L.ev_done) hipEventDestroy(L.ev_done);
-        if (L.st) hipStreamDestroy(L.st);
+        if (L.ev_start) (void)hipEventDestroy(L.ev_start);
+        if (L.ev_done) (void)hipEventDestroy(L.ev_done);
+        if (L.st) (void)hipStreamDestroy(L.st);
     }
     delete srv;
 }
