@@ -59,8 +59,11 @@ def _load():
             lib.fho_shift_center.restype = i64
             lib.fho_candidates.argtypes = [P, i32, i32, i32, i32, i32, P, P]
             lib.fho_candidates.restype = i32
-            lib.fho_shifts.argtypes = [i32, P, f64, f64, i32, f64, f64, P, P]
-            lib.fho_shifts.restype = None
+            lib.fho_row_shifts.argtypes = [i32, P, f64, f64, i32, f64, f64, i32, P]
+            lib.fho_row_shifts.restype = None
+            lib.fho_left_edges.argtypes = [i32, P, P, P, P, f64, P, i32, i64, f64, f64, f64,
+                                           i64, P, P, P]
+            lib.fho_left_edges.restype = ctypes.c_int
             lib.fho_inv_doppler.argtypes = [i32, P, P, P]
             lib.fho_inv_doppler.restype = None
             lib.fho_center.argtypes = [i32, i32, f64]
@@ -126,16 +129,36 @@ def set_threads(n: int) -> None:
     _load().fho_set_threads(int(n))
 
 
-def shifts(pm, grid):
-    """(G0, dG) int64 per FFT, in fixed-point fine bins (2^16 steps per bin)."""
+def row_shifts(pm, grid, s: int):
+    """Spin-down shifts G_is of row s for every FFT, int64, in fixed-point fine
+    bins (2^16 steps per bin)."""
     lib = _load()
     n = pm.t.shape[0]
-    g0 = np.zeros(n, np.int64)
-    dg = np.zeros(n, np.int64)
+    out = np.zeros(n, np.int64)
     t = np.ascontiguousarray(pm.t, dtype=np.float64)
-    lib.fho_shifts(n, _ptr(t), float(grid.t0), float(pm.t_fft), int(grid.kf),
-                   float(grid.fdot0), float(grid.dfdot), _ptr(g0), _ptr(dg))
-    return g0, dg
+    lib.fho_row_shifts(n, _ptr(t), float(grid.t0), float(pm.t_fft), int(grid.kf),
+                       float(grid.fdot0), float(grid.dfdot), int(s), _ptr(out))
+    return out
+
+
+def left_edges(pm, grid, nhat, peaks, rows):
+    """Fixed-point left stripe edges L_s of the (peak, row) pairs, int64, by
+    the same steps as ``hough_map`` (exact Doppler correction)."""
+    lib = _load()
+    t = np.ascontiguousarray(pm.t, dtype=np.float64)
+    v = np.ascontiguousarray(pm.v, dtype=np.float64).reshape(-1, 3)
+    off = np.ascontiguousarray(pm.offsets, dtype=np.int64)
+    bins = np.ascontiguousarray(pm.bins, dtype=np.int32)
+    n = np.ascontiguousarray(np.asarray(nhat, dtype=np.float64).reshape(3))
+    pk = np.ascontiguousarray(peaks, dtype=np.int64)
+    rw = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros(pk.shape[0], np.int64)
+    rc = lib.fho_left_edges(int(t.shape[0]), _ptr(off), _ptr(bins), _ptr(t), _ptr(v), float(pm.t_fft),
+                            _ptr(n), int(grid.kf), int(grid.b0), float(grid.fdot0), float(grid.dfdot),
+                            float(grid.t0), int(pk.shape[0]), _ptr(pk), _ptr(rw), _ptr(out))
+    if rc != 0:
+        raise ValueError("peak index out of range")
+    return out
 
 
 def inv_doppler(pm, nhat):

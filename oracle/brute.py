@@ -8,9 +8,9 @@ are IEEE binary64 with round-half-even ``round`` and exact ``math.floor``.
 
 Definitions (Eqs. fdopp, uno, due, ncount, ncountadap, freqres, sdstep), with
 Q = 2^16 fixed-point steps per fine bin:
-  S = (K_f T_FFT) Q; G0_i = rint((fdot0 tau_i) S); dG_i = rint((dfdot tau_i) S)
+  S = (K_f T_FFT) Q; G_is = rint(((fdot0 + s dfdot) tau_i) S)   (row s)
   r_i = 1 / (1 + ((v_x n_x + v_y n_y) + v_z n_z))
-  X = floor((K_f k r_i) Q); L_s = X - b0 Q - K_f Q/2 - G0_i - s dG_i
+  X = floor((K_f k r_i) Q); L_s = X - b0 Q - K_f Q/2 - G_is
   cell (s, b) counts the peak iff L_s <= b Q < L_s + K_f Q
 """
 from __future__ import annotations
@@ -21,10 +21,11 @@ QD = 65536.0
 QI = 1 << 16
 
 
-def _fft_terms(t_i, t0, t_fft, kf, fdot0, dfdot):
+def _row_shift(t_i, t0, t_fft, kf, fdot0, dfdot, s):
     tau = t_i - t0
     S = (float(kf) * t_fft) * QD
-    return round((fdot0 * tau) * S), round((dfdot * tau) * S)
+    fs = fdot0 + float(s) * dfdot
+    return round((fs * tau) * S)
 
 
 def _inv_doppler(vi, n):
@@ -36,24 +37,24 @@ def hough_map_cells(pm, grid, nhat, weights=None):
     """Cell-major map as a list of lists of floats."""
     n = [float(x) for x in nhat]
     kf, b0, nf, ns = int(grid.kf), int(grid.b0), int(grid.nf), int(grid.ns)
-    peaks = []  # (X, G0, dG, w)
+    peaks = []  # (X, FFT, w)
     for i in range(pm.t.shape[0]):
-        g0, dg = _fft_terms(float(pm.t[i]), float(grid.t0), float(pm.t_fft), kf,
-                            float(grid.fdot0), float(grid.dfdot))
         r = _inv_doppler([float(x) for x in pm.v[i]], n)
         w = 1.0 if weights is None else float(weights[i])
         for p in range(int(pm.offsets[i]), int(pm.offsets[i + 1])):
             k = int(pm.bins[p])
             X = math.floor((float(kf * k) * r) * QD)
-            peaks.append((X, g0, dg, w))
+            peaks.append((X, i, w))
     out = []
     for s in range(ns):
+        shift = [_row_shift(float(pm.t[i]), float(grid.t0), float(pm.t_fft), kf, float(grid.fdot0),
+                            float(grid.dfdot), s) for i in range(pm.t.shape[0])]
         row = []
         for b in range(nf):
             lab = b * QI
             acc = 0.0
-            for X, g0, dg, w in peaks:
-                L = X - b0 * QI - kf * (QI // 2) - g0 - s * dg
+            for X, i, w in peaks:
+                L = X - b0 * QI - kf * (QI // 2) - shift[i]
                 if L <= lab < L + kf * QI:
                     acc += w
             row.append(acc)

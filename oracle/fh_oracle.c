@@ -19,16 +19,20 @@
  *
  * The stripe edge is evaluated in an exactly specified fixed point with
  * Q = 2^16 steps per fine bin, so that integer maps can be compared bit for
- * bit:
+ * bit.  Every row s has its own spin-down fdot_s = fdot0 + s*dfdot (Eq.
+ * sdstep), and its shift is rounded once per row and FFT:
  *   S      = (K_f * T_FFT) * Q
- *   G0_i   = llrint((fdot0 * tau_i) * S),  dG_i = llrint((dfdot * tau_i) * S)
+ *   G_is   = llrint(((fdot0 + s*dfdot) * tau_i) * S)       (row s, FFT i)
  *   D      = 1 + ((vx*nx + vy*ny) + vz*nz),  r = 1 / D
  *   X      = floor(((double)(K_f*k) * r) * Q)             (corrected centre)
- *   L_s    = X - b0*Q - K_f*Q/2 - G0_i - s*dG_i           (left edge, row s)
+ *   L_s    = X - b0*Q - K_f*Q/2 - G_is                    (left edge, row s)
  *   bin b is touched  iff  L_s <= b*Q < L_s + K_f*Q
  * All double operations are IEEE binary64, round to nearest even, evaluated in
  * the order written and never contracted into FMAs (build with
- * -ffp-contract=off).
+ * -ffp-contract=off).  Against the real-valued edge of Eq. due (the same
+ * inputs in exact arithmetic) L_s lies within [-1.5, +0.5] quanta: the floor
+ * of X loses less than one quantum, the rounding of G_is at most half of one,
+ * and the binary64 products add ~1e-3 quanta at most.
  *
  * Per-FFT shift variant (the Doppler removal read as a plain shift of each
  * FFT's bins, computed at one reference frequency f_ref for the whole band):
@@ -57,16 +61,20 @@ static int64_t floor_div_q(int64_t a)
     return q;
 }
 
-/* Per-FFT spin-down shifts in fixed-point fine bins (Eqs. uno and sdstep). */
-void fho_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
-                double fdot0, double dfdot, int64_t *g0, int64_t *dg)
+/* Spin-down shift of row s for an FFT at tau = t_i - t0, in fixed-point fine
+ * bins (Eqs. uno and sdstep): the row's spin-down times tau, rounded once. */
+static int64_t row_shift(double tau, double S, double fdot0, double dfdot, int32_t s)
+{
+    double fs = fdot0 + (double)s * dfdot;
+    return llrint((fs * tau) * S);
+}
+
+/* Shifts of row s for every FFT: out[i] = G_is. */
+void fho_row_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
+                    double fdot0, double dfdot, int32_t s, int64_t *out)
 {
     double S = ((double)kf * t_fft) * QD;
-    for (int32_t i = 0; i < n_fft; ++i) {
-        double tau = t[i] - t0;
-        g0[i] = llrint((fdot0 * tau) * S);
-        dg[i] = llrint((dfdot * tau) * S);
-    }
+    for (int32_t i = 0; i < n_fft; ++i) out[i] = row_shift(t[i] - t0, S, fdot0, dfdot, s);
 }
 
 /* Doppler factor inverse r = 1/(1 + v.n) per FFT (Eq. fdopp). */
@@ -92,6 +100,41 @@ int64_t fho_shift_center(int32_t k, int32_t kf, double q, double r)
     return (int64_t)kf * (int64_t)k * QI - llrint((q * (1.0 - r)) * QD);
 }
 
+/* Stripe left edge at fdot = 0: E = X - b0*Q - K_f*Q/2. */
+static int64_t zero_spin_edge(int32_t k, int32_t kf, double r, int64_t b0, int32_t shift_mode, double q)
+{
+    int64_t x = shift_mode ? fho_shift_center(k, kf, q, r) : fho_center(k, kf, r);
+    return x - b0 * QI - (int64_t)kf * (QI / 2);
+}
+
+/*
+ * Left stripe edges L_s (fixed point) of sampled (peak, row) pairs of one sky
+ * direction, by the same steps as the map: out[j] = L for peak peak[j] in row
+ * row[j] (exact Doppler correction).  Returns 0, or -1 on a bad index.
+ */
+int fho_left_edges(int32_t n_fft, const int64_t *offsets, const int32_t *bins, const double *t,
+                   const double *v, double t_fft, const double *nhat, int32_t kf, int64_t b0,
+                   double fdot0, double dfdot, double t0, int64_t n_pairs, const int64_t *peak,
+                   const int32_t *row, int64_t *out)
+{
+    const double S = ((double)kf * t_fft) * QD;
+    const int64_t n_peaks = offsets[n_fft];
+    for (int64_t j = 0; j < n_pairs; ++j) {
+        int64_t p = peak[j];
+        if (p < 0 || p >= n_peaks) return -1;
+        /* FFT of the peak: last i with offsets[i] <= p */
+        int32_t lo = 0, hi = n_fft;
+        while (hi - lo > 1) {
+            int32_t m = lo + (hi - lo) / 2;
+            if (offsets[m] <= p) lo = m; else hi = m;
+        }
+        double r;
+        fho_inv_doppler(1, v + 3 * (int64_t)lo, nhat, &r);
+        out[j] = zero_spin_edge(bins[p], kf, r, b0, 0, 0.0) - row_shift(t[lo] - t0, S, fdot0, dfdot, row[j]);
+    }
+    return 0;
+}
+
 /*
  * Hough map of one sky direction, rows [row_lo, row_hi) only (the other rows
  * of `out` are left untouched).  out is [ns][nf] row-major, double, and is
@@ -108,22 +151,20 @@ int fho_hough_map_mode(int32_t n_fft, const int64_t *offsets, const int32_t *bin
     if (n_fft < 0 || kf < 1 || nf < 0 || ns < 0 || row_lo < 0 || row_hi > ns || row_lo > row_hi)
         return -1;
     int64_t n_peaks = offsets[n_fft];
-    int64_t *g0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_fft + 1));
-    int64_t *dg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_fft + 1));
+    double *tau = (double *)malloc(sizeof(double) * (size_t)(n_fft + 1));
     double *r = (double *)malloc(sizeof(double) * (size_t)(n_fft + 1));
     int64_t *edge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_peaks + 1));
-    if (!g0 || !dg || !r || !edge) {
-        free(g0); free(dg); free(r); free(edge);
+    if (!tau || !r || !edge) {
+        free(tau); free(r); free(edge);
         return -1;
     }
-    fho_shifts(n_fft, t, t0, t_fft, kf, fdot0, dfdot, g0, dg);
+    for (int32_t i = 0; i < n_fft; ++i) tau[i] = t[i] - t0;
+    const double S = ((double)kf * t_fft) * QD;
     fho_inv_doppler(n_fft, v, nhat, r);
-    /* stripe left edge at fdot = 0: E = X - b0*Q - K_f*Q/2 */
     const double q = ((double)kf * t_fft) * f_ref;
     for (int32_t i = 0; i < n_fft; ++i)
         for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p)
-            edge[p] = (shift_mode ? fho_shift_center(bins[p], kf, q, r[i]) : fho_center(bins[p], kf, r[i])) -
-                      b0 * QI - (int64_t)kf * (QI / 2);
+            edge[p] = zero_spin_edge(bins[p], kf, r[i], b0, shift_mode, q);
 
     const int64_t width = (int64_t)kf * QI;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -131,7 +172,7 @@ int fho_hough_map_mode(int32_t n_fft, const int64_t *offsets, const int32_t *bin
         double *row = out + (int64_t)s * nf;
         memset(row, 0, sizeof(double) * (size_t)nf);
         for (int32_t i = 0; i < n_fft; ++i) {
-            int64_t shift = g0[i] + (int64_t)s * dg[i];
+            int64_t shift = row_shift(tau[i], S, fdot0, dfdot, s);
             double wi = w ? w[i] : 1.0;
             for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
                 int64_t L = edge[p] - shift;
@@ -145,7 +186,7 @@ int fho_hough_map_mode(int32_t n_fft, const int64_t *offsets, const int32_t *bin
             }
         }
     }
-    free(g0); free(dg); free(r); free(edge);
+    free(tau); free(r); free(edge);
     return 0;
 }
 
