@@ -14,17 +14,21 @@
  * Exact integer definition (shared by every entry point), stripe edges in
  * units of Q = 2^-16 fine bins:
  *   tau_i = t_i - t0;  S = (K_f * T_FFT) * 2^16
- *   G0_i  = llrint((fdot0 * tau_i) * S);   dG_i = llrint((dfdot * tau_i) * S)
+ *   G_is  = llrint(((fdot0 + s*dfdot) * tau_i) * S)           (row s, FFT i)
  *   D     = 1 + ((vx*nx + vy*ny) + vz*nz);  r = 1 / D        (IEEE binary64,
  *   X     = floor(((double)(K_f * k) * r) * 2^16)             no FMA contraction)
- *   L_s   = X - b0*2^16 - K_f*2^15 - G0_i - s*dG_i
+ *   L_s   = X - b0*2^16 - K_f*2^15 - G_is
  *   fine bin b (0 <= b < nf) of row s (0 <= s < ns) gains w_i for peak (i, k)
  *   iff L_s <= b*2^16 < L_s + K_f*2^16.
  *   Bin b is labelled f0 = (b0 + b) / (K_f T_FFT); row s is fdot0 + s*dfdot.
- *   A grid whose largest step |dfdot tau_i| K_f T_FFT reaches 128 fine bins
- *   per row is rejected with FH_E_UNSUPPORTED (the tiles keep stripe edges
- *   in 32 bits and row steps in 24), and so is a peakmap with an FFT of
- *   65536 peaks or more.
+ *   L_s is within [-1.5, +0.5] Q of the real-valued stripe edge of Eq. due
+ *   for the same inputs, so a cell's membership differs from the exact
+ *   geometry only where a bin label lies within 1.5 Q of a stripe edge.
+ *   Rejected with FH_E_UNSUPPORTED: a grid whose largest step
+ *   |dfdot tau_i| K_f T_FFT reaches 128 fine bins per row (the tiles keep
+ *   tile-relative stripe edges in 32 bits), a peakmap with an FFT of 65536
+ *   peaks or more, and n_fft * (ns rounded up to 16) reaching 2^28 (the
+ *   per-row shift table is addressed with 31-bit byte offsets).
  *
  * Conventions
  *   - Every pointer named d_* is device memory on the context's device and is
@@ -242,7 +246,8 @@ fh_status fh_hough_map_f32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
  * d_w:    NULL (unweighted), or device float32 weights: w_stride = 0 means one
  *         [N] vector shared by all directions, w_stride = N means [n_sky][N].
  * d_out:  device [n_sky][n_sb][2] candidates, n_sb = ceil(nf / sel->width).
- * opts:   NULL for defaults (persistent schedule, library tile choice, graphs).
+ * opts:   NULL for defaults (persistent schedule, autotuned tile width, library
+ *         chunking, no graph capture).
  * Unweighted results are bit-exact with the definition above and identical for
  * both schedules; weighted results are identical for both schedules. */
 fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky,

@@ -1,8 +1,8 @@
 // HIP kernels of the frequency-Hough (FH) library for gfx950 (MI355X).
 //
 // Pipeline for one chunk of sky directions (Sec. "Frequency-Hough transform"):
-//   k_shifts       per FFT: spin-down shifts G0_i, dG_i in Q32.32 fine bins
-//                  (Eqs. uno, sdstep).                        sky independent
+//   k_row_shifts   per (FFT, spin-down row): the row's shift G_is in 2^-16
+//                  fine bins (Eqs. uno, sdstep).              sky independent
 //   k_weight_stats per weight vector: sum w, sum w^2, fixed-point bits F.
 //   k_prep         per (sky, peak): Doppler-corrected stripe edge Y (Eq.
 //                  fdopp, Eq. due) and per (sky, FFT) fixed-point weights.
@@ -67,31 +67,27 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
 }
 
 // ----------------------------------------------------------------------------
-// spin-down shifts: G0_i = rint((fdot0 tau_i) S), dG_i = rint((dfdot tau_i) S),
-// S = (K_f T_FFT) kQ (Eqs. uno, sdstep)
+// spin-down shifts (Eqs. uno, sdstep): row s has the spin-down
+// fdot_s = fdot0 + s dfdot, and FFT i's stripes in that row are shifted by
+//   G_is = rint((fdot_s tau_i) S),  tau_i = t_i - t0,  S = (K_f T_FFT) kQ
+// rounded once per row.  The table G[i][s] covers s < nsp (every row of the
+// padded row blocks; rows past the grid are computed by the same formula and
+// never reach the output).
 
-__global__ void k_shifts(int32_t n, const double *__restrict__ t, double t0, double S,
-                         double fdot0, double dfdot, int64_t *__restrict__ g0,
-                         int64_t *__restrict__ dg) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double tau = t[i] - t0;
-    double a = fdot0 * tau;
-    a = a * S;
-    double b = dfdot * tau;
-    b = b * S;
-    g0[i] = (int64_t)rint(a);
-    dg[i] = (int64_t)rint(b);
-}
-
-// Row terms of a tile: T[i][j] = -j dG_i (mod 2^32), the offset of row s0 + j
-// from row s0 of every tile.
-__global__ void k_row_terms(int32_t n_fft, const int64_t *__restrict__ dg,
-                            int32_t *__restrict__ rowt) {
-    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (x >= (int64_t)n_fft * kTileRows) return;
-    const int64_t i = x / kTileRows, j = x % kTileRows;
-    rowt[x] = (int32_t)(uint32_t)(uint64_t)(-j * dg[i]);
+__global__ void k_row_shifts(int32_t n_fft, int32_t nsp, const double *__restrict__ t, double t0,
+                             double S, double fdot0, double dfdot, int64_t *__restrict__ gsh) {
+    const int64_t n = (int64_t)n_fft * nsp;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = x / nsp;
+        const int32_t s = (int32_t)(x - i * nsp);
+        const double tau = t[i] - t0;
+        double fs = (double)s * dfdot;
+        fs = fdot0 + fs;
+        double a = fs * tau;
+        a = a * S;
+        gsh[x] = (int64_t)rint(a);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -146,16 +142,16 @@ __global__ void k_weight_stats(int32_t n, const float *__restrict__ w, int32_t w
 // per-peak stripe edge.  For peak (i, k) and sky n:
 //   r = 1 / (1 + ((vx nx + vy ny) + vz nz))                     (Eq. fdopp)
 //   X = floor(((double)(K_f k) r) kQ)
-//   Y = X - b0 kQ - K_f kQ/2 - G0_i + (kQ - 1)
+//   Y = X - b0 kQ - K_f kQ/2 + (kQ - 1)
 // so that the first fine bin of the stripe in row s is
-//   a_s = ceil((X - b0 kQ - K_f kQ/2 - G0_i - s dG_i) / kQ)
-//       = floor((Y - s dG_i) / kQ).
+//   a_s = ceil((X - b0 kQ - K_f kQ/2 - G_is) / kQ)
+//       = floor((Y - G_is) / kQ).
 // One wave per FFT; grid.y = sky slot.
 
 __global__ void __launch_bounds__(256) k_prep(
     int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ bins, const double *__restrict__ v,
-    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
+    const double *__restrict__ sky, int32_t kf, int64_t b0,
     int64_t *__restrict__ Y, const float *__restrict__ w, int32_t w_stride,
     const WeightStats *__restrict__ ws, int32_t ws_stride, uint32_t *__restrict__ wq,
     uint32_t *__restrict__ Y32, int32_t shift_mode, double q) {
@@ -170,7 +166,7 @@ __global__ void __launch_bounds__(256) k_prep(
     d = d + vi[2] * n[2];
     d = 1.0 + d;
     const double r = 1.0 / d;
-    int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+    int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) + (kQ - 1);
     if (shift_mode) c -= llrint((q * (1.0 - r)) * kQd);  // per-FFT shift at the reference
     // FFT i's edges start at offsets[i] + kYPad * i and are followed by kYPad
     // sentinels
@@ -208,14 +204,16 @@ __global__ void __launch_bounds__(256) k_prep(
 // two binary searches over the staged edges.  The window of a tile is the run
 // of peaks p with
 //   max_s a_s(p) >= jb W - (K_f - 1)   and   min_s a_s(p) < (jb + 1) W
-// over the group's rows s (a_s is monotone in Y, Y ascending within an FFT).
-// Consecutive threads write consecutive FFTs of a window row.
+// over the group's rows s (a_s is monotone in Y, Y ascending within an FFT;
+// G_is is monotone in s, so its extremes over the rows are those of the
+// first and last row).  Consecutive threads write consecutive FFTs of a
+// window row.
 
 __global__ void __launch_bounds__(256) k_front(
     int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ bins, const double *__restrict__ v,
-    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ g0,
-    const int64_t *__restrict__ dg, uint32_t *__restrict__ Y, const float *__restrict__ w,
+    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ gsh,
+    int32_t nsp, uint32_t *__restrict__ Y, const float *__restrict__ w,
     int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
     uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
     int2 *__restrict__ win, int32_t shift_mode, double q) {
@@ -244,7 +242,7 @@ __global__ void __launch_bounds__(256) k_front(
         d = 1.0 + d;
         const double r = 1.0 / d;
         s_r[threadIdx.x] = r;
-        int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) - g0[i] + (kQ - 1);
+        int64_t c = -b0 * kQ - (int64_t)kf * (kQ / 2) + (kQ - 1);
         if (shift_mode) c -= llrint((q * (1.0 - r)) * kQd);  // per-FFT shift at the reference
         s_c[threadIdx.x] = c;
         if (w != nullptr) {
@@ -307,9 +305,9 @@ __global__ void __launch_bounds__(256) k_front(
             const int64_t p1 = offsets[f + 1] + (int64_t)kYPad * f - pb;
             const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
             const int32_t s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
-            const int64_t q_lo = (int64_t)s_lo * dg[f], q_hi = (int64_t)s_hi * dg[f];
-            // max_s a_s = floor((Y - min q) / kQ) >= t  <=>  Y >= t kQ + min q
-            // min_s a_s = floor((Y - max q) / kQ) >= t  <=>  Y >= t kQ + max q
+            const int64_t q_lo = gsh[(int64_t)f * nsp + s_lo], q_hi = gsh[(int64_t)f * nsp + s_hi];
+            // max_s a_s = floor((Y - min G) / kQ) >= t  <=>  Y >= t kQ + min G
+            // min_s a_s = floor((Y - max G) / kQ) >= t  <=>  Y >= t kQ + max G
             const int64_t y_lo = ((int64_t)jb * W - (kf - 1)) * kQ + (q_lo < q_hi ? q_lo : q_hi);
             const int64_t y_hi = (int64_t)(jb + 1) * W * kQ + (q_lo < q_hi ? q_hi : q_lo);
             int a = (int)p0, b = (int)p1;
@@ -338,8 +336,8 @@ __global__ void __launch_bounds__(256) k_front(
 
 __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
                           const int64_t *__restrict__ Y, int64_t n_peaks,
-                          const int64_t *__restrict__ dg, int32_t ns, int32_t nrbg, int32_t nbb,
-                          int32_t W, int32_t kf, int2 *__restrict__ win) {
+                          const int64_t *__restrict__ gsh, int32_t nsp, int32_t ns, int32_t nrbg,
+                          int32_t nbb, int32_t W, int32_t kf, int2 *__restrict__ win) {
     const int32_t n_pad = win_stride(n_fft);
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nbb * n_pad) return;
@@ -356,8 +354,8 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
     if (s_hi > ns - 1) s_hi = ns - 1;
     const int64_t c0 = (int64_t)jb * W - (kf - 1);
     const int64_t wc = (int64_t)W + kf - 1;
-    const int64_t q_lo = (int64_t)s_lo * dg[i] + c0 * kQ;
-    const int64_t q_hi = (int64_t)s_hi * dg[i] + c0 * kQ;
+    const int64_t q_lo = gsh[(int64_t)i * nsp + s_lo] + c0 * kQ;
+    const int64_t q_hi = gsh[(int64_t)i * nsp + s_hi] + c0 * kQ;
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int64_t p0 = offsets[i] + (int64_t)kYPad * i, p1 = offsets[i + 1] + (int64_t)kYPad * i;
     // lo: first peak whose larger column is >= 0
@@ -397,8 +395,8 @@ __device__ __forceinline__ int floor_div_w(int64_t x, int W, float inv_w) {
 
 __global__ void __launch_bounds__(256) k_windows_sweep(
     int32_t n_fft, const int64_t *__restrict__ offsets, const int64_t *__restrict__ Y,
-    int64_t n_peaks, const int64_t *__restrict__ dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
-    int32_t kf, int2 *__restrict__ win) {
+    int64_t n_peaks, const int64_t *__restrict__ gsh, int32_t nsp, int32_t ns, int32_t nrbg, int32_t nbb,
+    int32_t W, int32_t kf, int2 *__restrict__ win) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int slot = blockIdx.y;
@@ -412,13 +410,13 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int p0 = (int)(offsets[i] + (int64_t)kYPad * i);
     const int p1 = (int)(offsets[i + 1] + (int64_t)kYPad * i);
-    const int64_t dG = dg[i];
+    const int64_t *gi = gsh + (int64_t)i * nsp;
     const float inv_w = 1.0f / (float)W;
     for (int g = 0; g < nrbg; ++g) {
         int2 *wg = win + ((int64_t)slot * nrbg + g) * nbb * (int64_t)n_pad + i;
         const int s_lo = g * kRowBlocksPerGroup * kTileRows;
         const int s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
-        const int64_t q_lo = (int64_t)s_lo * dG, q_hi = (int64_t)s_hi * dG;
+        const int64_t q_lo = gi[s_lo], q_hi = gi[s_hi];
         int prev_hi = -1;  // jhi of the peak before this chunk
         int prev_lo = 0;   // jlo of the peak before this chunk
         for (int pb = p0; pb < p1; pb += 64) {
@@ -640,13 +638,14 @@ __device__ __forceinline__ void lds_barrier() {
 // LDS tile: word (c, j) = c * 16 + j holds the stripe starts of column c
 // (fine bin jb*W - (K_f-1) + c) in row s0 + j; column W + K_f - 1 is a dump
 // column for updates that fall outside the tile.  The 16 lanes of a group
-// address 16 consecutive words, so an LDS atomic of a wave is bank-conflict
-// free whatever the stripe positions are.
+// address 16 consecutive words, so a group's part of an LDS atomic never
+// conflicts with itself (the four groups of a wave can still collide on the
+// bank halves that their columns map to).
 // One step of the accumulation.  Lane (group g, row j) adds the stripe of the
 // peak held by lane (g, U): its edge, already made relative to the tile
-// (v = Y - c0 kQ - s0 dG, exact in 32 bits for every peak of a window),
+// (v = Y - c0 kQ - G_{i,s0}, exact in 32 bits for every peak of a window),
 // reaches the group's 16 lanes through DPP row_newbcast:U fused into the add
-// of the lane's row term t = -j dG.  col = floor((v + t) / kQ) is the tile
+// of the lane's row term t = G_{i,s0} - G_{i,s0+j}.  col = floor((v + t) / kQ) is the tile
 // column of the stripe start in row s0 + j; columns outside
 // [0, W + K_f - 1) (negative ones wrap to large unsigned values) go to the
 // group's dump column.
@@ -698,13 +697,13 @@ __device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t,
 }
 
 // One block: four consecutive FFTs of a sorted run, entry 4 b + g in lane
-// group g.  Lane (g, j) holds its group's window, row term -j dG and weight,
-// and the stripe edges of its peaks in up to two chunks of 16.
+// group g.  Lane (g, j) holds its group's window, row term and weight, and
+// the stripe edges of its peaks in up to two chunks of 16.
 struct Quad {
     int g, run;          // block id claimed from the tile's counter; its run g % 16
     int lo, pk;          // window start; FFT place in the run << 16 | peak count
-    int32_t dg;          // row step dG of the group's FFT
-    uint32_t t, wq;      // row term -j dG (mod 2^32); fixed-point weight
+    uint32_t gb;         // G_{i,s0} of the group's FFT i (mod 2^32)
+    uint32_t t, wq;      // row term G_{i,s0} - G_{i,s0+j} (mod 2^32); fixed-point weight
     int cnt;             // peaks in the window (0 past the tile's blocks)
     int32_t q1, q2;      // chunk positions of the lane's peaks
     uint32_t y0, y1;     // low words of their stripe edges
@@ -1012,11 +1011,13 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     const int total = kTileWaves * nblk;  // blocks of a tile
     const int i_last = A.n_fft - 1;
     const int home = blockIdx.x % kXcds;
-    const __amdgpu_buffer_rsrc_t r_t = buf(A.rowt), r_dg = buf(A.dg);
+    const __amdgpu_buffer_rsrc_t r_g = buf(A.gsh);
+    const uint32_t nsp = (uint32_t)A.nsp;
 
     // per-tile buffers: window row, stripe edges and weights of the slot
     struct Bufs {
         __amdgpu_buffer_rsrc_t win, y, wq;
+        uint32_t s0;  // first row of the tile
     };
     auto tile_bufs = [&](int t) {
         int slot, rb, jb;
@@ -1026,7 +1027,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         b.win = buf(A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * n_pad);
         // low 32 bits of the stripe edges (all the tile needs: see stripe_word)
         b.y = buf(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
-        b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.dg);
+        b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.gsh);
+        b.s0 = (uint32_t)(rb * kTileRows);
         return b;
     };
     // Blocks are handed out dynamically: block g of a tile is block g / 16 of
@@ -1053,12 +1055,15 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     };
     // stripe edges, row terms and weights of block bb (stage 2): the chunk
     // sizes follow the largest window of the four groups, group 0's (the runs
-    // are sorted by window size)
+    // are sorted by window size).  The row terms come from the low words of
+    // the FFT's shifts of rows s0 and s0 + j (the host keeps N nsp below 2^28,
+    // so the byte offsets fit 31 bits).
     auto stage_y = [&](Quad &Q, const Bufs &B) {
         Q.cnt = Q.pk & 0xFFFF;
         const uint32_t fc = min((uint32_t)((Q.pk >> 16) * kTileWaves + Q.run), (uint32_t)i_last);
-        Q.t = ld_u32(r_t, (fc * kTileRows + (uint32_t)j) * 4u);
-        Q.dg = (int32_t)ld_u32(r_dg, fc * 8u);
+        const uint32_t go = (fc * nsp + B.s0) * 8u;
+        Q.gb = ld_u32(r_g, go);
+        Q.t = Q.gb - ld_u32(r_g, go + (uint32_t)j * 8u);
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
         Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
@@ -1094,10 +1099,9 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         if (tid == 0) s_cnt[par ^ 1] = 0;
         int slot, rb, jb;
         decode_tile(A, t, slot, rb, jb);
-        const int s0 = rb * kTileRows;
         const uint32_t c0q = (uint32_t)(jb * W - (kf - 1)) << kFrac;
         auto consume = [&](const Quad &Q) {
-            const uint32_t base = c0q + (uint32_t)__mul24(s0, Q.dg);  // |dG| < 2^23
+            const uint32_t base = c0q + Q.gb;
             uint32_t val = Q.wq;
             asm volatile("" : "+v"(val));
             const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
@@ -1404,7 +1408,7 @@ int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + kDumpCols) 
 int max_tile_bins(int kf, double step_bins) {
     const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dumps
     int w = words - kf + 1 - kDumpCols;                           // W + kf - 1 + dumps <= words
-    // the row base s0 dG is a 24-bit product: |dG| < 2^23 (128 fine bins)
+    // supported row steps: below 128 fine bins
     if (step_bins * kQd + 1.0 >= 8388608.0) return 0;
     // 32-bit tile-relative edges (see kFarEdge)
     const double m = ceil(step_bins) + 1.0;
@@ -1425,17 +1429,12 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_shifts(int32_t n_fft, const double *t, double t0, double t_fft, int32_t kf,
-                         double fdot0, double dfdot, int64_t *g0, int64_t *dg, hipStream_t st) {
-    const double S = ((double)kf * t_fft) * kQd;
-    k_shifts<<<grid_for(n_fft, 256), 256, 0, st>>>(n_fft, t, t0, S, fdot0, dfdot, g0, dg);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_terms(int32_t n_fft, const int64_t *dg, int32_t *rowt, hipStream_t st) {
-    const int64_t n = (int64_t)n_fft * kTileRows;
+hipError_t launch_row_shifts(int32_t n_fft, int32_t nsp, const double *t, double t0, double t_fft, int32_t kf,
+                             double fdot0, double dfdot, int64_t *gsh, hipStream_t st) {
+    const int64_t n = (int64_t)n_fft * nsp;
     if (n <= 0) return hipSuccess;
-    k_row_terms<<<grid_for(n, 256), 256, 0, st>>>(n_fft, dg, rowt);
+    const double S = ((double)kf * t_fft) * kQd;
+    k_row_shifts<<<grid_for(n, 256), 256, 0, st>>>(n_fft, nsp, t, t0, S, fdot0, dfdot, gsh);
     return hipGetLastError();
 }
 
@@ -1447,11 +1446,11 @@ hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int
 
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                        const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                       const int64_t *g0, int64_t *Y, const float *w, int32_t w_stride,
+                       int64_t *Y, const float *w, int32_t w_stride,
                        const WeightStats *ws, int32_t ws_stride, uint32_t *wq, uint32_t *Y32,
                        int32_t shift_mode, double q, hipStream_t st) {
     dim3 grid((n_fft + 3) / 4, n_slots);
-    k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, Y, w, w_stride,
+    k_prep<<<grid, 256, 0, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, Y, w, w_stride,
                                  ws, ws_stride, wq, Y32, shift_mode, q);
     return hipGetLastError();
 }
@@ -1464,7 +1463,7 @@ int front_ffts_per_block(int32_t max_per_fft) {
 
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                         const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                        const int64_t *g0, const int64_t *dg, uint32_t *Y, const float *w,
+                        const int64_t *gsh, int32_t nsp, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
                         int2 *win, int32_t shift_mode, double q, hipStream_t st) {
@@ -1472,7 +1471,7 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
     dim3 grid(win_stride(n_fft) / F, n_slots);
     const size_t lds = ((size_t)F * (max_per_fft + kYPad) * 8 + 255) / 256 * 256;
     if (F > kFrontMaxF || lds > (size_t)kFrontLdsBytes) return hipErrorInvalidValue;
-    k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, g0, dg, Y,
+    k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, gsh, nsp, Y,
                                                w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win,
                                                shift_mode, q);
     return hipGetLastError();
@@ -1491,14 +1490,14 @@ hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t
 }
 
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
-                          const int64_t *dg, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+                          const int64_t *gsh, int32_t nsp, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
                           int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st) {
     if (method == 0) {
         dim3 grid(grid_for((int64_t)nbb * win_stride(n_fft), 256), nrbg, n_slots);
-        k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+        k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gsh, nsp, ns, nrbg, nbb, W, kf, win);
     } else {
         dim3 grid((win_stride(n_fft) + 3) / 4, n_slots);
-        k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, dg, ns, nrbg, nbb, W, kf, win);
+        k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gsh, nsp, ns, nrbg, nbb, W, kf, win);
     }
     return hipGetLastError();
 }

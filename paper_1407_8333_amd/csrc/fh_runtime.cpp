@@ -117,16 +117,16 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf g0, dg, rowt, Y, Y64, win, wsort, colmax, wq, ws, sky, qctr;
+    DevBuf gsh, Y, Y64, win, wsort, colmax, wq, ws, sky, qctr;
     PinnedBuf h_sky;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&g0, &dg, &rowt, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (const DevBuf *b : {&gsh, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&g0, &dg, &rowt, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (DevBuf *b : {&gsh, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             b->release();
         h_sky.release();
     }
@@ -170,6 +170,7 @@ namespace {
 
 struct Plan {
     int W, nrb, nbb, nrbg;
+    int nsp;  // rows of the spin-down shift table (every row of the row blocks)
     int64_t tiles_per_sky;
 };
 
@@ -177,6 +178,7 @@ Plan make_plan(const fh_grid &g, int W) {
     Plan p;
     p.W = W;
     p.nrb = (g.ns + kTileRows - 1) / kTileRows;
+    p.nsp = p.nrb * kTileRows;
     p.nbb = (g.nf + W - 1) / W;
     p.nrbg = (p.nrb + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
     p.tiles_per_sky = (int64_t)p.nrb * p.nbb;
@@ -219,6 +221,10 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     if (!(gmax < 1e12)) return fail(FH_E_INVALID, "spin-down shifts exceed the fixed-point range");
     if (pm->max_per_fft >= 65536)
         return fail(FH_E_UNSUPPORTED, "an FFT holds %d peaks; at most 65535 are supported", pm->max_per_fft);
+    // the tiles address the shift table [N][rows rounded up to 16] with 31-bit byte offsets
+    const int64_t nsp = (int64_t)(g->ns + kTileRows - 1) / kTileRows * kTileRows;
+    if ((int64_t)pm->n_fft * nsp >= ((int64_t)1 << 28))
+        return fail(FH_E_UNSUPPORTED, "n_fft x spin-down rows = %lld reaches 2^28", (long long)pm->n_fft * nsp);
     if (max_tile_bins(g->kf, row_step_bins(pm, g)) < 64)
         return fail(FH_E_UNSUPPORTED, "spin-down step of %.6g fine bins per row is too large for a tile",
                     row_step_bins(pm, g));
@@ -287,10 +293,9 @@ struct Timed {
 };
 
 struct ChunkBufs {
-    int64_t *g0, *dg;
+    int64_t *gsh;  // [N][nsp] spin-down shifts of every row
     uint32_t *Y;   // low words of the stripe edges (what the tiles read)
     int64_t *Y64;  // full stripe edges, only for the unfused window methods
-    int32_t *rowt;
     int2 *win, *wsort;
     unsigned long long *colmax;
     uint32_t *wq;
@@ -314,9 +319,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
                            int slots, int n_sky, bool weighted, hipStream_t st, ChunkBufs &b) {
     const int64_t N = pm->n_fft;
     fh_status s;
-    if ((s = ctx->cur->g0.ensure(8 * N, st))) return s;
-    if ((s = ctx->cur->dg.ensure(8 * N, st))) return s;
-    if ((s = ctx->cur->rowt.ensure((size_t)4 * kTileRows * N, st))) return s;
+    if ((s = ctx->cur->gsh.ensure((size_t)8 * N * p.nsp, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)4 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if (needs_full_edges(ctx, pm) &&
         (s = ctx->cur->Y64.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st)))
@@ -329,9 +332,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->sky.ensure((size_t)24 * n_sky, st))) return s;
     if ((s = ctx->cur->qctr.ensure(4 * kXcds, st))) return s;
     if ((s = ctx->err.ensure(4, st))) return s;
-    b.g0 = (int64_t *)ctx->cur->g0.ptr;
-    b.dg = (int64_t *)ctx->cur->dg.ptr;
-    b.rowt = (int32_t *)ctx->cur->rowt.ptr;
+    b.gsh = (int64_t *)ctx->cur->gsh.ptr;
     b.Y = (uint32_t *)ctx->cur->Y.ptr;
     b.Y64 = (int64_t *)ctx->cur->Y64.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
@@ -360,8 +361,8 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.n_slots = slots;
     a.Y = b.Y;
     a.win = b.wsort;
-    a.dg = b.dg;
-    a.rowt = b.rowt;
+    a.gsh = b.gsh;
+    a.nsp = p.nsp;
     a.wq = weighted ? b.wq : nullptr;
     a.ws = weighted ? b.ws : nullptr;
     a.ws_stride = ws_stride;
@@ -395,8 +396,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                         int slots, const double *d_sky, const float *d_w, int w_stride,
                         const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
-    HIP_OK(launch_shifts(pm->n_fft, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.g0, b.dg, st));
-    HIP_OK(launch_row_terms(pm->n_fft, b.dg, b.rowt, st));
+    HIP_OK(launch_row_shifts(pm->n_fft, p.nsp, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.gsh, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
@@ -406,15 +406,15 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     const double q = sm ? shift_reference_bins(ctx, pm, g) : 0.0;
     if (F > 0) {
         HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
-                            g->b0, b.g0, b.dg, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
+                            g->b0, b.gsh, p.nsp, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
                             p.nrbg, p.nbb, p.W, F, pm->max_per_fft, b.win, sm, q, st));
         HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
         return FH_OK;
     }
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
-                       g->kf, g->b0, b.g0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, sm, q,
+                       g->kf, g->b0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, sm, q,
                        st));
-    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.dg, g->ns, p.nrbg, p.nbb,
+    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.gsh, p.nsp, g->ns, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
     HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
     return FH_OK;
@@ -1157,7 +1157,8 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->n_row_blocks = p.nrb;
     out->n_bin_blocks = p.nbb;
     out->workspace_bytes = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
-                           8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky;
+                           8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky +
+                           8 * (int64_t)pm->n_fft * p.nsp;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
 }
@@ -1220,7 +1221,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.wsort, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
-        (uint64_t)(uintptr_t)b.g0, (uint64_t)(uintptr_t)b.dg, (uint64_t)(uintptr_t)b.rowt,
+        (uint64_t)(uintptr_t)b.gsh,
         (uint64_t)(uintptr_t)b.qctr, (uint64_t)(uintptr_t)b.Y64, (uint64_t)ctx->window_method,
         (uint64_t)ctx->doppler_mode, bits(ctx->doppler_fref)};
     fh_ctx::GraphEntry *ge = nullptr;
@@ -1332,7 +1333,7 @@ int64_t search_footprint(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid 
     const int64_t N = pm->n_fft;
     const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
                             8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
-    return 16 * N + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
+    return 8 * N * p.nsp + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
 }
 
 }  // namespace
