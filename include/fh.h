@@ -239,6 +239,22 @@ fh_status fh_hough_map_f32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
                            const float *d_w, const fh_grid *grid, float *d_map,
                            void *stream);
 
+/* Allocation-free variant of fh_hough_map_i32, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same bit-exact map;
+ * it calls no allocating routine.  Its workspace (shift table, stripe edges,
+ * peak windows) lives in a static 64 MiB device array that each GPU holds
+ * until the process ends; the array's address on each device is taken when
+ * the first context on that device is created.  A map needing more than
+ * 64 MiB is rejected with FH_E_UNSUPPORTED before anything is enqueued: the
+ * need is about 8 n_fft ceil16(ns) + 4 (n_peaks + 16 n_fft) + 16 x (row groups
+ * of 64 rows) x (tiles along the band) x (n_fft rounded up to 192) bytes.
+ * Every call on a GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU (different streams or contexts without
+ * ordering) race, so serialise them, e.g. on one stream. */
+fh_status fh_hough_map_i32_static(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[3],
+                                  const fh_grid *grid, int32_t *d_map, void *stream);
+
 /* ---- candidates (many sky directions) ------------------------------------ */
 
 /* Sub-band candidates of n_sky maps without materialising them.

@@ -218,6 +218,16 @@ def fh_hough_map_i32(ctx: Context, dpm: DevicePeakmap, nhat, grid, out=None, str
     return out
 
 
+def fh_hough_map_i32_static(ctx: Context, dpm: DevicePeakmap, nhat, grid, out: torch.Tensor, stream=None):
+    """fh_hough_map_i32 without any device allocation in the library: the
+    workspace is the library's static per-GPU scratch; `out` is caller-owned."""
+    assert out.dtype == torch.int32 and out.is_contiguous() and tuple(out.shape) == (grid.ns, grid.nf)
+    g = grid_struct(grid)
+    check(_lib.fh_hough_map_i32_static(ctx.handle, dpm.handle, _nhat(nhat), ctypes.byref(g),
+                                       ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
 def fh_hough_map_f32(ctx: Context, dpm: DevicePeakmap, nhat, weights: torch.Tensor, grid,
                      out=None, stream=None):
     """Weighted Hough map [ns][nf] float32; weights: device float32 [N]."""

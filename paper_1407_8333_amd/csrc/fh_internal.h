@@ -75,6 +75,8 @@ struct TileArgs {
 // ---- launchers (fh_kernels.hip) ----
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+// p[0..2] = (x, y, z), written by a kernel (no copy from host memory)
+hipError_t launch_set_f64x3(double *p, double x, double y, double z, hipStream_t st);
 // G[i][s] = rint(((fdot0 + s dfdot) (t_i - t0)) (K_f T_FFT) 2^16), s < nsp
 hipError_t launch_row_shifts(int32_t n_fft, int32_t nsp, const double *t, double t0, double t_fft, int32_t kf,
                              double fdot0, double dfdot, int64_t *gsh, hipStream_t st);

@@ -60,6 +60,14 @@ __global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n, unsign
         p[i] = v;
 }
 
+__global__ void k_set_f64x3(double *__restrict__ p, double x, double y, double z) {
+    if (threadIdx.x == 0) {
+        p[0] = x;
+        p[1] = y;
+        p[2] = z;
+    }
+}
+
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -1420,6 +1428,11 @@ int max_tile_bins(int kf, double step_bins) {
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     k_fill_u64<<<grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f64x3(double *p, double x, double y, double z, hipStream_t st) {
+    k_set_f64x3<<<1, 64, 0, st>>>(p, x, y, z);
     return hipGetLastError();
 }
 

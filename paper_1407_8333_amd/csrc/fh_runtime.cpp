@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -18,6 +19,14 @@
 #include "fh_internal.h"
 
 using namespace fh;
+
+// Scratch memory of fh_hough_map_i32_static (callers that cannot allocate):
+// one copy of this array per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: the device address of
+// each GPU's copy is taken once, with that device current, when the first
+// context on it is created (scratch_init), and only that address is used.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -39,6 +48,26 @@ fh_status fail(fh_status s, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                          \
             return fail(FH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
     } while (0)
+
+// Device address of each GPU's copy of `scratch` (nullptr until taken).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Take the address of the current device's copy of `scratch` (once per
+// device).  Devices past kMaxDevices keep no address; the entry point that
+// needs it then reports FH_E_UNSUPPORTED.
+fh_status scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return FH_OK;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FH_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(FH_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return FH_OK;
+}
 
 // A device buffer that only grows.  Growing synchronises the stream first so
 // that no enqueued kernel still uses the old allocation.
@@ -420,6 +449,9 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     return FH_OK;
 }
 
+fh_status enqueue_map(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, const float *d_w,
+                      const ChunkBufs &b, void *out, hipStream_t st);
+
 fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[3],
                            const float *d_w, const fh_grid *g, void *out, void *stream) {
     fh_status s;
@@ -433,6 +465,14 @@ fh_status hough_map_common(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
     ChunkBufs b;
     if ((s = ensure_workspace(ctx, pm, g, p, 1, 1, weighted, st, b))) return s;
     if ((s = upload_sky(ctx, nhat, 1, b, st))) return s;
+    return enqueue_map(ctx, pm, g, p, d_w, b, out, st);
+}
+
+// Front and tiles of one direction's map (the direction already in b.sky).
+fh_status enqueue_map(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, const float *d_w,
+                      const ChunkBufs &b, void *out, hipStream_t st) {
+    fh_status s;
+    const bool weighted = d_w != nullptr;
     if ((s = enqueue_front(ctx, pm, g, p, 1, b.sky, d_w, 0, b, st))) return s;
     TileArgs a = tile_args(pm, g, p, 1, b, weighted, 0);
     a.map_i32 = weighted ? nullptr : (int32_t *)out;
@@ -625,6 +665,8 @@ fh_status fh_ctx_create(int32_t device, fh_ctx **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(FH_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
     HIP_OK(init_kernel_attributes());
+    fh_status ss = scratch_init(device);
+    if (ss) return ss;
     fh_ctx *c = new fh_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
@@ -802,29 +844,29 @@ fh_status fh_peakmap_from_spectra(fh_ctx *ctx, int32_t n_fft, int32_t n_bins, in
     }
     hipStream_t st = (hipStream_t)stream;
     const int32_t cap = n_bins / 2 + 1;  // strict local maxima are never adjacent
-    int32_t *scratch = nullptr, *counts = nullptr;
+    int32_t *rows_buf = nullptr, *counts = nullptr;
     const size_t b_off = 8 * (size_t)(n_fft + 1), b_t = 8 * (size_t)n_fft, b_v = 24 * (size_t)n_fft;
-    if (hipMalloc(&scratch, 4 * (size_t)n_fft * cap) != hipSuccess || hipMalloc(&counts, 4 * (size_t)n_fft) != hipSuccess ||
+    if (hipMalloc(&rows_buf, 4 * (size_t)n_fft * cap) != hipSuccess || hipMalloc(&counts, 4 * (size_t)n_fft) != hipSuccess ||
         hipMalloc(&pm->d_offsets, b_off) != hipSuccess || hipMalloc(&pm->d_t, b_t) != hipSuccess ||
         hipMalloc(&pm->d_v, b_v) != hipSuccess) {
-        if (scratch) (void)hipFree(scratch);
+        if (rows_buf) (void)hipFree(rows_buf);
         if (counts) (void)hipFree(counts);
         fh_peakmap_release(ctx, pm);
         return fail(FH_E_NOMEM, "device allocation for the peakmap failed");
     }
     std::vector<int64_t> h_off(n_fft + 1);
-    hipError_t e = launch_pm_rows(n_fft, n_bins, ld, d_sp, d_sar, k0, theta, cap, scratch, counts, st);
+    hipError_t e = launch_pm_rows(n_fft, n_bins, ld, d_sp, d_sar, k0, theta, cap, rows_buf, counts, st);
     if (e == hipSuccess) e = launch_pm_scan(n_fft, counts, pm->d_offsets, st);
     if (e == hipSuccess) e = hipMemcpyAsync(h_off.data(), pm->d_offsets, b_off, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     const int64_t P = e == hipSuccess ? h_off[n_fft] : 0;
     if (e == hipSuccess && hipMalloc(&pm->d_bins, 4 * (size_t)std::max<int64_t>(1, P)) != hipSuccess)
         e = hipErrorOutOfMemory;
-    if (e == hipSuccess) e = launch_pm_pack(n_fft, cap, scratch, pm->d_offsets, pm->d_bins, st);
+    if (e == hipSuccess) e = launch_pm_pack(n_fft, cap, rows_buf, pm->d_offsets, pm->d_bins, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pm->d_t, t, b_t, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pm->d_v, v, b_v, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(scratch);
+    (void)hipFree(rows_buf);
     (void)hipFree(counts);
     if (e != hipSuccess) {
         fh_peakmap_release(ctx, pm);
@@ -1172,6 +1214,77 @@ fh_status fh_hough_map_f32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
                            const float *d_w, const fh_grid *grid, float *d_map, void *stream) {
     if (!d_w) return fail(FH_E_INVALID, "weights pointer is NULL");
     return hough_map_common(ctx, pm, nhat, d_w, grid, d_map, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Pieces of the unweighted map path carved out of `scratch` (256-byte aligned
+// byte offsets).  Every piece a kernel reads is written earlier in the same
+// call (edges, their padding, every window entry including the padding FFTs,
+// the shift table and the direction), so nothing has to start at zero; the
+// error flag and the queue counters are only read on paths this call does not
+// take (weights, the persistent schedule).
+struct StaticLayout {
+    size_t sky, err, qctr, gsh, y, y64, win, wsort, total;
+};
+
+StaticLayout static_layout(const fh_ctx *ctx, const fh_peakmap *pm, const Plan &p) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ys = (size_t)y_stride(pm->n_peaks, pm->n_fft);
+    const size_t wins = (size_t)8 * p.nrbg * p.nbb * win_stride(pm->n_fft);
+    StaticLayout L{};
+    size_t o = 0;
+    L.sky = o;   o += al(24);
+    L.err = o;   o += al(4);
+    L.qctr = o;  o += al(4 * kXcds);
+    L.gsh = o;   o += al((size_t)8 * pm->n_fft * p.nsp);
+    L.y = o;     o += al(4 * ys);
+    L.y64 = o;   if (needs_full_edges(ctx, pm)) o += al(8 * ys);
+    L.win = o;   o += al(wins);
+    L.wsort = o; o += al(wins);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+fh_status fh_hough_map_i32_static(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[3],
+                                  const fh_grid *g, int32_t *d_map, void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if ((s = check_grid(pm, g))) return s;
+    if ((s = check_sky(nhat))) return s;
+    if (!d_map) return fail(FH_E_INVALID, "output map pointer is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, 0));
+    const StaticLayout L = static_layout(ctx, pm, p);
+    if (L.total > kStaticScratchBytes)
+        return fail(FH_E_UNSUPPORTED, "this map needs %zu bytes of scratch; the static scratch holds %zu",
+                    L.total, kStaticScratchBytes);
+    void *base = ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!base) return fail(FH_E_UNSUPPORTED, "no static scratch on device %d", ctx->device);
+    char *c = static_cast<char *>(base);
+    ChunkBufs b{};
+    b.sky = reinterpret_cast<double *>(c + L.sky);
+    b.err = reinterpret_cast<int32_t *>(c + L.err);
+    b.qctr = reinterpret_cast<int32_t *>(c + L.qctr);
+    b.colmax = reinterpret_cast<unsigned long long *>(c + L.qctr);  // not written by the map path
+    b.gsh = reinterpret_cast<int64_t *>(c + L.gsh);
+    b.Y = reinterpret_cast<uint32_t *>(c + L.y);
+    b.Y64 = reinterpret_cast<int64_t *>(c + L.y64);
+    b.win = reinterpret_cast<int2 *>(c + L.win);
+    b.wsort = reinterpret_cast<int2 *>(c + L.wsort);
+    HIP_OK(launch_set_f64x3(b.sky, nhat[0], nhat[1], nhat[2], st));
+    // no profiling spans here: recording one can create an event
+    const bool was = ctx->profiling;
+    ctx->profiling = false;
+    s = enqueue_map(ctx, pm, g, p, nullptr, b, d_map, st);
+    ctx->profiling = was;
+    return s;
 }
 
 fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, const double *sky,

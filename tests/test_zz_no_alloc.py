@@ -1,0 +1,68 @@
+"""The allocation-free map entry point (fh_hough_map_i32_static) against
+fh_hough_map_i32, through the C ABI: two calls in a row, the second on a
+smaller input, must give the same bit-exact maps; no device memory is taken
+by the call; a map too large for the static scratch is rejected before
+anything is enqueued."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1407_8333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_static_map_equals_the_allocating_entry_point_twice():
+    import torch
+    from paper_1407_8333_amd import api
+    print("case: static map, sky-100hz with 1500 FFTs then plain-50hz", flush=True)
+    big = synth.workload("sky-100hz", seed=5, n_fft=1500)
+    small = synth.workload("plain-50hz", seed=6)
+    with api.Context(0) as ctx:
+        d_big = ctx.upload(big.pm)
+        d_small = ctx.upload(small.pm)
+        out_big = torch.full((big.grid.ns, big.grid.nf), -7, dtype=torch.int32, device="cuda")
+        out_small = torch.full((small.grid.ns, small.grid.nf), -7, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        api.fh_hough_map_i32_static(ctx, d_big, big.sky[0], big.grid, out_big)
+        api.fh_hough_map_i32_static(ctx, d_small, small.sky[0], small.grid, out_small)
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        # the library's workspace for these maps is several MB: none was taken
+        assert free0 - free1 < (1 << 20), (free0, free1)
+        s_big = out_big.cpu().numpy()
+        s_small = out_small.cpu().numpy()
+        ref_big = api.fh_hough_map_i32(ctx, d_big, big.sky[0], big.grid).cpu().numpy()
+        ref_small = api.fh_hough_map_i32(ctx, d_small, small.sky[0], small.grid).cpu().numpy()
+        np.testing.assert_array_equal(s_big, ref_big)
+        np.testing.assert_array_equal(s_small, ref_small)
+        np.testing.assert_array_equal(s_small, oracle.hough_map(small.pm, small.grid, small.sky[0]).astype(np.int32))
+        assert s_big.sum() > 0
+        # a second round, larger after smaller, still agrees
+        api.fh_hough_map_i32_static(ctx, d_big, big.sky[0], big.grid, out_big)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out_big.cpu().numpy(), ref_big)
+        d_big.release()
+        d_small.release()
+
+
+def test_static_map_rejects_what_the_scratch_cannot_hold():
+    import torch
+    from paper_1407_8333_amd import api, _lib
+    print("case: static map over the scratch limit", flush=True)
+    rng = synth.rng_for(31)
+    pm = synth.random_peakmap(2000, 1024.0, 100_000, 100_040, 0.05, rng)
+    t0 = 0.5 * (pm.t[0] + pm.t[-1])
+    # 2000 FFTs x 8192 rows: the shift table alone is 131 MB
+    grid = synth.Grid(kf=10, b0=10 * 100_000, nf=400, ns=8192, fdot0=-1e-14, dfdot=1e-18, t0=t0)
+    with api.Context(0) as ctx:
+        dpm = ctx.upload(pm)
+        out = torch.zeros((grid.ns, grid.nf), dtype=torch.int32, device="cuda")
+        with pytest.raises(_lib.FHError) as e:
+            api.fh_hough_map_i32_static(ctx, dpm, synth.sky_uniform(1, rng)[0], grid, out)
+        assert e.value.status == _lib.FH_E_UNSUPPORTED
+        assert "scratch" in str(e.value)
+        torch.cuda.synchronize()
+        assert int(out.abs().sum()) == 0
+        dpm.release()
