@@ -271,6 +271,21 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky,
                               const fh_grid *grid, const fh_select *sel,
                               const fh_options *opts, fh_candidate *d_out, void *stream);
 
+/* Column maxima of n_sky maps without materialising them: for every
+ * direction and fine bin b, the largest map value over the spin-down rows
+ * and the smallest row holding it -- what candidate selection ranks over
+ * "all the possible spin-down values" (Sec. "Selection of first level
+ * candidates"), and the map's projection on the frequency axis by maximum.
+ * Arguments as fh_hough_candidates (use_graph is ignored).
+ * d_value: device float32 [n_sky][nf]: the count (exact) or the weighted
+ *          sum (the fixed-point sum times 2^-F, rounded to float32 as the
+ *          candidates' value);
+ * d_row:   device int32 [n_sky][nf]: smallest row s with H[s][b] = max.
+ * Unweighted results are bit-exact with the definition above. */
+fh_status fh_hough_colmax(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, const double *sky,
+                          const float *d_w, int32_t w_stride, const fh_grid *grid,
+                          const fh_options *opts, float *d_value, int32_t *d_row, void *stream);
+
 /* ---- refined grid ---------------------------------------------------- */
 
 /* The peaks of `pm` whose natural bin k lies in [k_lo, k_hi), as a new device

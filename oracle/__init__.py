@@ -197,19 +197,6 @@ def candidates(hmap: np.ndarray, width: int, excl: int = 4, sep: int = 8):
     return idx, val
 
 
-def p0(theta: float) -> float:
-    """Noise peak probability of a local maximum above theta (Eq. p0)."""
-    import math
-    return math.exp(-theta) - math.exp(-2 * theta) + math.exp(-3 * theta) / 3.0
-
-
-def critical_ratio(n, n_fft: int, theta: float = 2.5):
-    """CR = (n - N p0) / sqrt(N p0 (1 - p0)) (Eq. cr)."""
-    q = p0(theta)
-    return (np.asarray(n, dtype=np.float64) - n_fft * q) / np.sqrt(n_fft * q * (1.0 - q))
-
-
-def critical_ratio_weighted(n, w_sum: float, w2_sum: float, theta: float = 2.5):
-    """Weighted analogue: (n - p0 sum w) / sqrt(p0 (1 - p0) sum w^2)."""
-    q = p0(theta)
-    return (np.asarray(n, dtype=np.float64) - q * w_sum) / np.sqrt(q * (1.0 - q) * w2_sum)
+# the statistics closed forms live in one place, oracle/stats.py (pinned to
+# the paper's printed numbers in tests/test_paper_values.py)
+from .stats import critical_ratio, critical_ratio_weighted, p0  # noqa: E402,F401

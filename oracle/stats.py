@@ -47,6 +47,21 @@ def p_lambda_paper_integral(theta: float, lam: float) -> float:
     return integrate.quad(f, theta, 60.0, limit=200)[0]
 
 
+def critical_ratio(n, n_fft: int, theta: float = 2.5, q=None):
+    """Eq. cr: CR = (n - N p0) / sqrt(N p0 (1 - p0)); q overrides p0(theta)."""
+    q = p0(theta) if q is None else q
+    return (np.asarray(n, dtype=np.float64) - n_fft * q) / np.sqrt(n_fft * q * (1.0 - q))
+
+
+def critical_ratio_weighted(n, w_sum: float, w2_sum: float, theta: float = 2.5, q=None):
+    """Critical ratio of a weighted count n = sum_i w_i n_i (Eq. ncountadap):
+    with independent n_i ~ Bernoulli(p0) in noise, E n = p0 sum w and
+    Var n = p0 (1 - p0) sum w^2, so CR = (n - p0 sum w) / sqrt(p0 (1 - p0) sum w^2).
+    Unit weights give Eq. cr."""
+    q = p0(theta) if q is None else q
+    return (np.asarray(n, dtype=np.float64) - q * w_sum) / np.sqrt(q * (1.0 - q) * w2_sum)
+
+
 def hough_mean_std(n_fft: int, eta: float):
     """Eq. houghmean: binomial mean and standard deviation of a map cell."""
     return n_fft * eta, math.sqrt(n_fft * eta * (1.0 - eta))

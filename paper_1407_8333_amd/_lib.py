@@ -118,6 +118,8 @@ _PROTOS = {
                        ctypes.POINTER(fh_plan_info)], ctypes.c_int),
     "fh_hough_map_i32": ([P, P, P, ctypes.POINTER(fh_grid), P, P], ctypes.c_int),
     "fh_hough_map_i32_static": ([P, P, P, ctypes.POINTER(fh_grid), P, P], ctypes.c_int),
+    "fh_hough_colmax": ([P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.POINTER(fh_grid),
+                         ctypes.POINTER(fh_options), P, P, P], ctypes.c_int),
     "fh_hough_map_f32": ([P, P, P, P, ctypes.POINTER(fh_grid), P, P], ctypes.c_int),
     "fh_hough_candidates": ([P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.POINTER(fh_grid),
                              ctypes.POINTER(fh_select), ctypes.POINTER(fh_options), P, P],
@@ -197,6 +199,7 @@ fh_peakmap_bytes = _fwd("fh_peakmap_bytes")
 fh_plan_query = _fwd("fh_plan_query")
 fh_hough_map_i32 = _fwd("fh_hough_map_i32")
 fh_hough_map_i32_static = _fwd("fh_hough_map_i32_static")
+fh_hough_colmax = _fwd("fh_hough_colmax")
 fh_hough_map_f32 = _fwd("fh_hough_map_f32")
 fh_hough_candidates = _fwd("fh_hough_candidates")
 fh_ctx_profile = _fwd("fh_ctx_profile")

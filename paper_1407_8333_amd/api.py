@@ -276,6 +276,32 @@ def fh_hough_candidates(ctx: Context, dpm: DevicePeakmap, sky, grid, sel,
     return out
 
 
+def fh_hough_colmax(ctx: Context, dpm: DevicePeakmap, sky, grid, weights: Optional[torch.Tensor] = None,
+                    schedule: int = 1, tile_bins: int = 0, sky_chunk: int = 0, stream=None):
+    """Per-bin column maxima of n_sky maps: (value float32 [n_sky, nf],
+    smallest row holding it int32 [n_sky, nf])."""
+    sky = np.ascontiguousarray(np.asarray(sky, dtype=np.float64).reshape(-1, 3))
+    n_sky = sky.shape[0]
+    dev = "cuda:%d" % ctx.device
+    value = torch.empty((n_sky, grid.nf), dtype=torch.float32, device=dev)
+    row = torch.empty((n_sky, grid.nf), dtype=torch.int32, device=dev)
+    w_ptr, w_stride = None, 0
+    if weights is not None:
+        assert weights.dtype == torch.float32 and weights.is_cuda and weights.is_contiguous()
+        if weights.dim() == 2:
+            assert tuple(weights.shape) == (n_sky, dpm.n_fft)
+            w_stride = dpm.n_fft
+        else:
+            assert weights.numel() == dpm.n_fft
+        w_ptr = ctypes.c_void_p(weights.data_ptr())
+    g = grid_struct(grid)
+    o = _lib.fh_options(int(schedule), int(tile_bins), int(sky_chunk), 0)
+    check(_lib.fh_hough_colmax(ctx.handle, dpm.handle, n_sky, sky.ctypes.data, w_ptr, w_stride,
+                               ctypes.byref(g), ctypes.byref(o), ctypes.c_void_p(value.data_ptr()),
+                               ctypes.c_void_p(row.data_ptr()), _stream(stream)))
+    return value, row
+
+
 def decode_candidates(raw: torch.Tensor) -> dict:
     """Split a [.., 8] int32 candidate tensor into numpy fields."""
     a = raw.detach().cpu().numpy()

@@ -155,6 +155,9 @@ hipError_t launch_bin_counts(int32_t n_fft, const int64_t *offsets, const int32_
 // robust statistic: hist needs 2 x_max + 1 entries; out[0] = m1, out[1] = m2
 hipError_t launch_robust(const int32_t *x, int32_t n, int32_t x_max, int32_t *hist, int64_t *s2, double *out,
                          int32_t *err, hipStream_t st);
+// decoded column maxima of n_slots directions: value [slot][nf], row [slot][nf]
+hipError_t launch_colmax_decode(const unsigned long long *colmax, int32_t nf, int32_t n_slots, const WeightStats *ws,
+                                int32_t ws_stride, float *value, int32_t *row, hipStream_t st);
 hipError_t launch_colmax_values(const unsigned long long *colmax, int32_t nf, int32_t *out, hipStream_t st);
 int tile_lds_bytes(int W, int kf);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).

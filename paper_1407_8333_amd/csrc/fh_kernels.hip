@@ -1834,7 +1834,35 @@ __global__ void k_colmax_values(const unsigned long long *__restrict__ colmax, i
     if (b < nf) out[b] = (int32_t)(colmax[b] >> 32);
 }
 
+// Column maxima of n_slots directions decoded: value (the count, or the
+// weighted sum as k_select forms it from the fixed point) and smallest row.
+__global__ void k_colmax_decode(const unsigned long long *__restrict__ colmax, int32_t nf, int32_t n_slots,
+                                const WeightStats *__restrict__ ws, int32_t ws_stride,
+                                float *__restrict__ value, int32_t *__restrict__ row) {
+    const int64_t n = (int64_t)n_slots * nf;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = colmax[x];
+        const uint32_t v = (uint32_t)(k >> 32);
+        float f = (float)v;
+        if (ws != nullptr) {
+            const int64_t slot = x / nf;
+            f = f * (float)ldexp(1.0, -ws[slot * ws_stride].frac_bits);
+        }
+        value[x] = f;
+        row[x] = (int32_t)(0xFFFFFFFFu - (uint32_t)k);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_colmax_decode(const unsigned long long *colmax, int32_t nf, int32_t n_slots, const WeightStats *ws,
+                                int32_t ws_stride, float *value, int32_t *row, hipStream_t st) {
+    const int64_t n = (int64_t)n_slots * nf;
+    if (n <= 0) return hipSuccess;
+    k_colmax_decode<<<grid_for(n, 256) > 8192 ? 8192 : grid_for(n, 256), 256, 0, st>>>(colmax, nf, n_slots, ws,
+                                                                                       ws_stride, value, row);
+    return hipGetLastError();
+}
 
 hipError_t launch_slice(int32_t n_fft, const int64_t *offsets, const int32_t *bins, int32_t k_lo, int32_t k_hi,
                         int64_t *first, int32_t *counts, int64_t *out_offsets, int32_t *out_bins,

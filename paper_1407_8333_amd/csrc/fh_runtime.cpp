@@ -486,20 +486,28 @@ fh_status enqueue_map(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const
     return FH_OK;
 }
 
-// chunk: as many directions as a bounded workspace holds (fewer launches,
-// more tiles per persistent launch)
+// chunk: as many directions as a 48 GiB workspace holds (a sixth of the
+// MI355X's HBM), at most 4096: fewer launches, more tiles per persistent
+// launch (the 256 Hz batch of 1024 directions, 27 GB, is one launch)
 int default_chunk(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
     if (requested > 0) return requested;
     const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
-    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)16 << 30) / std::max<int64_t>(1, per_sky));
-    return (int)std::min<int64_t>(by_mem, 256);
+    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)48 << 30) / std::max<int64_t>(1, per_sky));
+    return (int)std::min<int64_t>(by_mem, 4096);
 }
 
 // Enqueue the search of n_sky directions (already uploaded to b.sky) in
 // chunks of `chunk`; sel == nullptr skips candidate selection.
+// Optional per-bin column maxima of every direction, decoded: value [n_sky][nf]
+// and smallest row holding it [n_sky][nf].
+struct ColmaxOut {
+    float *value = nullptr;
+    int32_t *row = nullptr;
+};
+
 fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
                      int n_sky, const float *d_w, int w_stride, int schedule, const fh_select *sel,
-                     fh_candidate *d_out, const ChunkBufs &b, hipStream_t st) {
+                     fh_candidate *d_out, const ChunkBufs &b, hipStream_t st, ColmaxOut cm_out = {}) {
     fh_status s;
     const bool weighted = d_w != nullptr;
     for (int32_t base = 0; base < n_sky; base += chunk) {
@@ -520,6 +528,11 @@ fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const 
             HIP_OK(launch_tiles(a, weighted, false, true, false, (int32_t)n_tiles, 0, st));
         }
         if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns * slots;
+        if (cm_out.value)
+            HIP_OK(launch_colmax_decode(b.colmax, g->nf, slots, weighted ? b.ws : nullptr,
+                                        weighted ? (w_stride == 0 ? 0 : 1) : 0,
+                                        cm_out.value + (int64_t)base * g->nf, cm_out.row + (int64_t)base * g->nf,
+                                        st));
         if (sel) {
             Timed timed_sel(ctx, st, kSpanSelect);
             HIP_OK(launch_select(b.colmax, g->nf, slots, *sel, base, pm->n_fft, weighted ? b.ws : nullptr,
@@ -1373,6 +1386,40 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
     }
     if (ctx->profiling) ctx->prof_updates += pm->n_peaks * (int64_t)g->ns * n_sky;
     return FH_OK;
+}
+
+fh_status fh_hough_colmax(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, const double *sky, const float *d_w,
+                          int32_t w_stride, const fh_grid *g, const fh_options *opts, float *d_value,
+                          int32_t *d_row, void *stream) {
+    fh_status s;
+    if ((s = check_ctx(ctx))) return s;
+    if ((s = check_grid(pm, g))) return s;
+    if (n_sky < 1) return fail(FH_E_INVALID, "n_sky=%d < 1", n_sky);
+    if (!sky) return fail(FH_E_INVALID, "sky is NULL");
+    for (int32_t k = 0; k < n_sky; ++k)
+        if ((s = check_sky(sky + 3 * (int64_t)k))) return s;
+    if (!d_value || !d_row) return fail(FH_E_INVALID, "output pointer is NULL");
+    if (d_w && w_stride != 0 && w_stride != pm->n_fft)
+        return fail(FH_E_INVALID, "w_stride must be 0 or n_fft");
+    fh_options o{FH_SCHED_PERSISTENT, 0, 0, 0};
+    if (opts) o = *opts;
+    if (o.schedule != FH_SCHED_PLAIN && o.schedule != FH_SCHED_PERSISTENT)
+        return fail(FH_E_INVALID, "unknown schedule %d", o.schedule);
+    if (o.tile_bins < 0 || o.sky_chunk < 0) return fail(FH_E_INVALID, "negative option");
+    hipStream_t st = (hipStream_t)stream;
+    const bool weighted = d_w != nullptr;
+    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g, weighted)) == ctx->tuned.end())
+        if ((s = autotune(ctx, pm, g, n_sky, sky, d_w, w_stride, st))) return s;
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins, weighted));
+    int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(ctx, pm, g, p, o.sky_chunk);
+    chunk = std::min(chunk, n_sky);
+    ChunkBufs b;
+    if ((s = ensure_workspace(ctx, pm, g, p, chunk, n_sky, weighted, st, b))) return s;
+    if ((s = upload_sky(ctx, sky, n_sky, b, st))) return s;
+    ColmaxOut cm;
+    cm.value = d_value;
+    cm.row = d_row;
+    return run_search(ctx, pm, g, p, chunk, n_sky, d_w, w_stride, o.schedule, nullptr, nullptr, b, st, cm);
 }
 
 fh_status fh_ctx_profile(fh_ctx *ctx, int32_t enable) {

@@ -75,6 +75,50 @@ def test_weighted_map_100hz_full_size(ctx):
     _assert_weighted_close(got, ref, w.weights)
 
 
+def _fixed_point_bits(weights, n_fft, adjacent):
+    """F of the library's weight fixed point: the largest F <= 40 with
+    2^(F+1) <= ((2^32 - 1) / m - N / 2) / sum w (m = 2 with adjacent bins)."""
+    m = 2 if adjacent else 1
+    lim = (4294967295.0 / m - 0.5 * n_fft) / float(np.sum(np.asarray(weights, np.float64)))
+    f = 0
+    while f < 40 and 2.0 ** (f + 1) <= lim:
+        f += 1
+    return f
+
+
+@pytest.mark.parametrize("name,n_fft", [("sky-100hz", 1500), ("batch-256hz", None)])
+def test_weighted_map_wide_weight_range(ctx, name, n_fft):
+    """Weights U(0.02, 1.5), as adaptive weights near an antenna-pattern zero
+    produce.  Every cell is within the stated fixed-point bound
+    n_c 2^-(F+1) + 2^-24 |H| (n_c: contributions to the cell), and within
+    1e-5 max(|H|, mean w) on these inputs; the candidates and their CR follow."""
+    import torch
+    api = _api()
+    w = synth.workload(name, seed=77, n_fft=n_fft, n_sky=1)
+    print("case: wide weights", name, w.pm.n_fft, flush=True)
+    rng = synth.rng_for(78)
+    wts = rng.uniform(0.02, 1.5, w.pm.n_fft).astype(np.float32)
+    nhat = w.sky[0]
+    got = _gpu_map(ctx, w.pm, w.grid, nhat, weights=wts)
+    ref = oracle.hough_map(w.pm, w.grid, nhat, weights=wts.astype(np.float64))
+    n_c = oracle.hough_map(w.pm, w.grid, nhat)
+    adjacent = any(np.any(np.diff(w.pm.bins[w.pm.offsets[i]:w.pm.offsets[i + 1]]) == 1)
+                   for i in range(w.pm.n_fft))
+    F = _fixed_point_bits(wts, w.pm.n_fft, adjacent)
+    err = np.abs(got.astype(np.float64) - ref)
+    bound = n_c * 2.0 ** -(F + 1) + 2.0 ** -24 * np.abs(ref) + 1e-12
+    assert np.all(err <= bound), (F, float((err - bound).max()))
+    _assert_weighted_close(got, ref, wts)
+    dpm = ctx.upload(w.pm)
+    raw = api.fh_hough_candidates(ctx, dpm, w.sky, w.grid, w.sel, weights=torch.as_tensor(wts, device="cuda"))
+    torch.cuda.synchronize()
+    ctx.check()
+    dec = api.decode_candidates(raw)
+    idx, val = oracle.candidates(ref, w.sel.width, w.sel.excl, w.sel.sep)
+    _check_candidates(dec, 0, idx, val, w.pm.n_fft, w.sel.theta, weighted_map=ref, weights=wts)
+    dpm.release()
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_random_small_maps_edge_cases(ctx, seed):
     """Ragged tiles, rows not a multiple of 16, K_f from 1 to 64, empty FFTs,
@@ -154,6 +198,14 @@ def _check_candidates(dec, s, ref_idx, ref_val, n_fft, theta, weighted_map=None,
                 tol = REL_TOL * max(ref_val[sb, r], float(np.mean(weights)))
                 assert weighted_map[row, b] >= ref_val[sb, r] - 2 * tol
                 assert dec["value"][s, sb, r] == pytest.approx(ref_val[sb, r], abs=2 * tol)
+                # weighted critical ratio of the oracle's best value; the GPU's
+                # value may differ by 2 tol, which moves CR by 2 tol / sigma
+                w64 = np.asarray(weights, np.float64)
+                ws, w2 = float(w64.sum()), float((w64 * w64).sum())
+                q = oracle.p0(theta)
+                sigma = math.sqrt(q * (1 - q) * w2)
+                cr = float(oracle.critical_ratio_weighted(ref_val[sb, r], ws, w2, theta))
+                assert abs(float(dec["cr"][s, sb, r]) - cr) <= 2 * tol / sigma + 1e-5 * (1 + abs(cr)), (sb, r)
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
@@ -183,6 +235,46 @@ def test_candidates_batch_256hz_sampled_skies(ctx):
     for s in (0, 5, 11):
         _, idx, val = _candidates_ref(w.pm, w.grid, w.sky[s], w.sel)
         _check_candidates(dec, s, idx, val, w.pm.n_fft, w.sel.theta)
+    dpm.release()
+
+
+def _colmax_ref(m):
+    """Per-bin maximum over rows and the smallest row holding it."""
+    top = m.max(axis=0)
+    row = np.argmax(m == top[None, :], axis=0)
+    return top, row
+
+
+def test_column_maxima_batch_256hz_every_bin(ctx):
+    """Column maxima of four directions at full size (583 rows = 37 row blocks
+    merged by 64-bit atomics, 40960 bins), unweighted, bit for bit against the
+    oracle's map in every bin; both schedules; one weighted direction within
+    tolerance."""
+    import torch
+    api = _api()
+    w = synth.workload("batch-256hz", n_sky=4)
+    print("case: column maxima batch-256hz, 4 directions", flush=True)
+    dpm = ctx.upload(w.pm)
+    val, row = api.fh_hough_colmax(ctx, dpm, w.sky, w.grid, schedule=1)
+    val0, row0 = api.fh_hough_colmax(ctx, dpm, w.sky, w.grid, schedule=0)
+    torch.cuda.synchronize()
+    assert torch.equal(val, val0) and torch.equal(row, row0)
+    val, row = val.cpu().numpy(), row.cpu().numpy()
+    for s in range(4):
+        top, arg = _colmax_ref(oracle.hough_map(w.pm, w.grid, w.sky[s]))
+        np.testing.assert_array_equal(val[s], top.astype(np.float32))
+        np.testing.assert_array_equal(row[s], arg)
+    wt = torch.as_tensor(w.weights, device="cuda")
+    vw, rw = api.fh_hough_colmax(ctx, dpm, w.sky[1:2], w.grid, weights=wt)
+    torch.cuda.synchronize()
+    ctx.check()
+    m = oracle.hough_map(w.pm, w.grid, w.sky[1], weights=w.weights.astype(np.float64))
+    top, _ = _colmax_ref(m)
+    vw, rw = vw.cpu().numpy()[0], rw.cpu().numpy()[0]
+    tol = REL_TOL * np.maximum(top, float(np.mean(w.weights)))
+    assert np.all(np.abs(vw.astype(np.float64) - top) <= tol)
+    # the reported row holds a value within tolerance of the maximum
+    assert np.all(m[rw, np.arange(w.grid.nf)] >= top - 2 * tol)
     dpm.release()
 
 

@@ -70,3 +70,62 @@ def test_p_lambda_small_signal_limit():
     d_exact = (stats.p_lambda_paper_integral(th, lam) - stats.p0(th)) / lam
     d_approx = (stats.p_lambda_approx(th, lam) - stats.p0(th)) / lam
     assert d_exact == pytest.approx(d_approx, rel=2e-3)
+
+
+# ---------------------------------------------------------------------------
+# Eq. cr and its weighted form
+
+
+def test_cr_of_the_printed_mean_and_deviation():
+    """Eq. cr with the printed p0 puts the printed mean of the number count at
+    CR = 0 and the mean plus one printed deviation at CR = 1 (N = 61594)."""
+    n, q = int(G["n_fft_1yr_1024s"]), G["p0_theta_2.5"]
+    mu, sd = G["hough_mean_N61594"], G["hough_std_N61594"]
+    assert stats.critical_ratio(mu, n, q=q) == pytest.approx(0.0, abs=0.002)
+    assert stats.critical_ratio(mu + sd, n, q=q) == pytest.approx(1.0, abs=0.002)
+    assert stats.critical_ratio(mu - 2 * sd, n, q=q) == pytest.approx(-2.0, abs=0.004)
+
+
+def test_cr_of_the_table3_count_thresholds():
+    """Table III's n_thr column, read without the sqrt(2) of Eq. nthr_gauss,
+    sits at CR = CR_thr / sqrt(2) of the same row (to the integer rounding
+    of n_thr: 1/sigma)."""
+    q = G["p0_theta_2.5"]
+    for n, nthr, crthr in zip(G["table3_n_fft"], G["table3_nthr"], G["table3_crthr"]):
+        sigma = math.sqrt(n * q * (1 - q))
+        assert stats.critical_ratio(nthr, int(n), q=q) == pytest.approx(crthr / math.sqrt(2.0),
+                                                                         abs=1.0 / sigma + 0.01)
+
+
+def test_weighted_cr_reduces_to_eq_cr_for_unit_weights():
+    n = np.array([0.0, 17.0, 75.5, 200.0])
+    for n_fft in (1, 200, 61594):
+        np.testing.assert_array_equal(stats.critical_ratio_weighted(n, float(n_fft), float(n_fft)),
+                                      stats.critical_ratio(n, n_fft))
+
+
+def test_weighted_cr_is_invariant_to_a_common_weight_scale():
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.05, 3.0, 500)
+    n = 0.3 * w.sum()
+    base = stats.critical_ratio_weighted(n, w.sum(), (w * w).sum())
+    for c in (1e-3, 0.5, 7.0, 1e4):
+        cw = c * w
+        assert stats.critical_ratio_weighted(c * n, cw.sum(), (cw * cw).sum()) == pytest.approx(base, rel=1e-12)
+
+
+def test_weighted_cr_is_standard_in_noise():
+    """Weighted counts n = sum_i w_i n_i with n_i ~ Bernoulli(p0) (a noise-only
+    cell of Eq. ncountadap): the weighted CR has mean 0 and deviation 1.
+    Weights U(0.05, 3) make sum w^2 differ from sum w, so a variance built
+    from sum w (or a mean without p0) would fail."""
+    rng = np.random.default_rng(8333)
+    q = stats.p0(2.5)
+    w = rng.uniform(0.05, 3.0, 3000)
+    hits = rng.random((4000, w.size)) < q
+    n = hits.astype(np.float64) @ w
+    cr = stats.critical_ratio_weighted(n, w.sum(), (w * w).sum())
+    assert float(np.mean(cr)) == pytest.approx(0.0, abs=0.05)
+    assert float(np.std(cr)) == pytest.approx(1.0, abs=0.03)
+    wrong = (n - q * w.sum()) / np.sqrt(q * (1 - q) * w.sum())
+    assert abs(float(np.std(wrong)) - 1.0) > 0.2
