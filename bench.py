@@ -3,8 +3,10 @@
 One step = the whole hot path over one batch: for every sky direction of the
 workload, Doppler correction, stripe edges, peak windows, the LDS histogram
 tiles with their row sums and per-bin maxima, and sub-band candidate
-selection (fh_hough_candidates, persistent schedule).  Inputs (peakmap and
-weights) are resident in device memory before the timed region.
+selection (fh_hough_candidates, persistent schedule, all directions in one
+persistent tile launch, replayed as one captured hipGraph on its own
+stream).  Inputs (peakmap and weights) are resident in device memory before
+the timed region.
 
 Prints one JSON line (metric: Hough cell-updates/s = input peaks x spin-down
 rows x sky directions per second).
@@ -25,7 +27,9 @@ if ROOT not in sys.path:
 
 # LDS atomic issue rate of gfx950: one wave64 ds_add_u32 every 4 clocks per
 # CU (16 lanes/clk), 256 CUs, 2.4 GHz.  One cell update = one LDS atomic.
+# The live probe (libfh_probe.so) measures what a CU sustains.
 LDS_ATOMIC_PEAK_TOPS = 256 * 16 * 2.4e9 / 1e12
+PROBE_LIB = os.path.join(ROOT, "paper_1407_8333_amd", "libfh_probe.so")
 WORKLOAD_TEXT = {
     "batch-256hz": "batch-256hz: 1024 sky directions (Fibonacci grid), 1 Hz band at 256 Hz, "
                    "T_FFT 4096 s, 6300 FFTs, ~2.3M peaks, 583 spin-down rows [-1e-8, 1e-9] Hz/s, "
@@ -56,6 +60,15 @@ def parse():
                     help="arrival rate as a fraction of the measured serving capacity")
     ap.add_argument("--doppler", default="exact", choices=["exact", "shift"],
                     help="Doppler correction: exact per peak (default) or one shift per FFT")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of hipGraph replays")
+    ap.add_argument("--sky-chunk", type=int, default=0,
+                    help="directions per persistent launch (0 = library choice: all 1024 in one)")
+    ap.add_argument("--variant-steps", type=int, default=3,
+                    help="steps timed for each eager / 4-launch variant (0 disables them)")
+    ap.add_argument("--large-sky", type=int, default=4096,
+                    help="directions of the large-band leg (0 disables it)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the LDS-atomic probe")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB moved by one plain device copy before the timed steps "
                          "(reference dispatch for hardware byte counters)")
@@ -154,6 +167,61 @@ def cpu_baseline(w, rows_arg, target_s=20.0):
     return {"value": updates / dt, "unit": "cell-updates/s", "cores": oracle.max_threads(),
             "kind": "oracle",
             "sample": "%s, %d peaks (%.3g cell updates, %.1f s)" % (what, w.pm.n_peaks, updates, dt)}
+
+
+def lds_probe():
+    """Live LDS-atomic microbenchmark: lanes per shader clock per CU and the
+    chip-wide rate for three address patterns (libfh_probe.so)."""
+    import ctypes
+    lib = ctypes.CDLL(PROBE_LIB)
+    f = lib.fhp_lds_atomic
+    d = ctypes.POINTER(ctypes.c_double)
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, d, d, d]
+    f.restype = ctypes.c_int
+    out = {}
+    for mode, name in [(0, "conflict_free"), (1, "random"), (2, "tile_pattern")]:
+        rate, lpc, ms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = f(mode, 2000, 1024, ctypes.byref(rate), ctypes.byref(lpc), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError("LDS probe failed with HIP error %d" % rc)
+        out[name] = {"lanes_per_clk_per_cu": lpc.value, "tops": rate.value / 1e12}
+    return out
+
+
+def large_band_leg(ctx, n_sky, steps=2):
+    """The large-band configuration at full size: 10 Hz at 1024 Hz, T_FFT
+    1024 s, 25000 FFTs (~20M peaks), 147 rows, 4096 directions, FP32 weights;
+    one warm-up step (autotuning), then `steps` timed steps."""
+    import torch
+
+    from paper_1407_8333_amd import api, synth
+    w = synth.workload("large-1024hz", n_sky=n_sky)
+    dpm = ctx.upload(w.pm)
+    wt = torch.as_tensor(w.weights, device="cuda")
+    out = torch.empty((n_sky, api.n_subbands(w.grid, w.sel), 2, 8), dtype=torch.int32, device="cuda")
+    api.fh_hough_candidates(ctx, dpm, w.sky, w.grid, w.sel, weights=wt, out=out)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.fh_hough_candidates(ctx, dpm, w.sky, w.grid, w.sel, weights=wt, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pr = ctx.profile_read()
+    ctx.profile(False)
+    plan = ctx.plan(dpm, w.grid, 0)
+    dpm.release()
+    cells = w.pm.n_peaks * w.grid.ns * n_sky * steps
+    launch_ms = pr["tiles_ms"] / max(1, pr["tiles_launches"])
+    achieved = pr["cell_updates"] / max(1, pr["tiles_launches"]) / (launch_ms * 1e-3) / 1e12
+    return {"workload": WORKLOAD_TEXT["large-1024hz"] + ", %d directions, FP32 weights" % n_sky,
+            "n_sky": n_sky, "n_peaks": w.pm.n_peaks, "steps": steps,
+            "value": cells / dt, "unit": "cell-updates/s", "ms_per_step": dt * 1e3 / steps,
+            "tile_launches_per_step": pr["tiles_launches"] / steps, "tile": [plan["tile_rows"], plan["tile_bins"]],
+            "kernel_split_ms_per_step": {"tiles": pr["tiles_ms"] / steps, "front": pr["front_ms"] / steps,
+                                         "select": pr["select_ms"] / steps},
+            "roofline": {"bound": "lds_atomic", "achieved": achieved, "peak": LDS_ATOMIC_PEAK_TOPS,
+                         "unit": "TOP/s", "frac": achieved / LDS_ATOMIC_PEAK_TOPS, "launch_ms": launch_ms}}
 
 
 SERVE_BANDS = [(8192.0, 40.0), (8192.0, 110.0), (4096.0, 180.0), (4096.0, 450.0),
@@ -260,11 +328,25 @@ def main():
     dpm = ctx.upload(w.pm)
     wt = None if w.weights is None else torch.as_tensor(w.weights, device=dev)
     out = torch.empty((n_sky, api.n_subbands(grid, sel), 2, 8), dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # a created stream: graph capture needs one
 
-    def step():
-        api.fh_hough_candidates(ctx, dpm, w.sky, grid, sel, weights=wt, schedule=1,
-                                tile_bins=args.tile_bins, out=out)
+    def step(graph=not args.no_graph, chunk=args.sky_chunk):
+        with torch.cuda.stream(stream):
+            api.fh_hough_candidates(ctx, dpm, w.sky, grid, sel, weights=wt, schedule=1,
+                                    tile_bins=args.tile_bins, sky_chunk=chunk, use_graph=1 if graph else 0,
+                                    out=out, stream=stream)
+
+    def timed(n, **kw):
+        """ms per step of n steps (events on the launch stream), after one untimed step."""
+        step(**kw)
+        stream.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n):
+            step(**kw)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / n
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -290,12 +372,33 @@ def main():
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    prof = ctx.profile_read()
+    prof_graph = ctx.profile_read()
     ctx.profile(False)
     step_ms = [a.elapsed_time(b) for a, b in ev]
     ms_per_step = wall * 1e3 / args.steps
     total_cells = cells_per_sky * n_sky * args.steps
     value = total_cells / wall
+    ctx.check()
+
+    # Kernel timing: a graph replay is one span, so the tile kernel's launch
+    # duration comes from the same launch configuration run eagerly, each
+    # kernel bracketed by HIP events on the launch stream.
+    n_eager = max(3, args.variant_steps)
+    step(graph=False)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(n_eager):
+        step(graph=False)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / n_eager
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    variants = {"graph_ms_per_step": ms_per_step, "eager_ms_per_step": eager_ms,
+                "tile_launches_per_step": prof["tiles_launches"] / n_eager}
+    if args.variant_steps > 0 and n_sky > 256:
+        variants["eager_4x256_ms_per_step"] = timed(args.variant_steps, graph=False, chunk=256)
+        variants["graph_4x256_ms_per_step"] = timed(args.variant_steps, graph=True, chunk=256)
 
     # plain per-sky schedule on a subset of the same directions
     n_plain = min(args.plain_sky, n_sky)
@@ -318,6 +421,7 @@ def main():
                  "ms_per_sky": dt * 1e3 / n_plain,
                  "tile_kernel_ms_per_launch": pp["tiles_ms"] / max(1, pp["tiles_launches"])}
 
+    probe = None if args.no_probe else lds_probe()
     tiles_ms_avg = prof["tiles_ms"] / max(1, prof["tiles_launches"])
     cells_per_launch = prof["cell_updates"] / max(1, prof["tiles_launches"])
     achieved = cells_per_launch / (tiles_ms_avg * 1e-3) / 1e12
@@ -339,27 +443,37 @@ def main():
                    "n_sky": n_sky, "n_fft": w.pm.n_fft, "n_peaks": w.pm.n_peaks,
                    "ns": grid.ns, "nf": grid.nf, "kf": grid.kf,
                    "weighted": wt is not None, "schedule": "persistent", "doppler": args.doppler,
-                   "tile": [plan["tile_rows"], plan["tile_bins"]]},
+                   "tile": [plan["tile_rows"], plan["tile_bins"]],
+                   "launch": "one hipGraph replay per step" if not args.no_graph else "eager launches",
+                   "tile_launches_per_step": variants["tile_launches_per_step"]},
         "p50_ms_per_step": pct(step_ms, 50),
         "p99_ms_per_step": pct(step_ms, 99),
         "batched_vs_plain": None if plain is None else value / plain["value"],
         "plain": plain,
-        "kernel_split_ms_per_step": {"tiles": prof["tiles_ms"] / args.steps,
-                                     "front": prof["front_ms"] / args.steps,
-                                     "select": prof["select_ms"] / args.steps},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": LDS_ATOMIC_PEAK_TOPS,
+        "launch_variants": variants,
+        "kernel_split_ms_per_step": {"tiles": prof["tiles_ms"] / n_eager,
+                                     "front": prof["front_ms"] / n_eager,
+                                     "select": prof["select_ms"] / n_eager},
+        "roofline": {"bound": "lds_atomic", "achieved": achieved, "peak": LDS_ATOMIC_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / LDS_ATOMIC_PEAK_TOPS,
+                     "peak_basis": "16 ds_add_u32 lanes per clock per CU x 256 CUs x 2.4 GHz",
+                     "probe": probe,
                      "traffic": committed_traffic(args.workload, n_sky, plan["tile_bins"], wt is not None),
                      "valu_cobound": valu_cobound(achieved, args.workload, n_sky, plan["tile_bins"],
                                                   wt is not None),
                      "kernel": "k_tiles_persistent (one op = one ds_add_u32 cell update)",
                      "launch_ms": tiles_ms_avg, "cells_per_launch": cells_per_launch},
     }
+    if args.large_sky > 0 and args.workload == "batch-256hz":
+        dpm.release()
+        dpm = None
+        res["large_band"] = large_band_leg(ctx, args.large_sky)
     if args.serve_requests > 0:
         res["serving"] = serve_bench(ctx, args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
-    dpm.release()
+    if dpm is not None:
+        dpm.release()
     ctx.close()
     print(json.dumps(res), flush=True)
 
