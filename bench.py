@@ -54,7 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of one direction the CPU oracle computes (0 = auto)")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream (for device traces of the lanes)")
+    ap.add_argument("--serve-lanes", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the Poisson serving run (0 disables it)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured serving capacity")
@@ -224,45 +227,99 @@ def large_band_leg(ctx, n_sky, steps=2):
                          "unit": "TOP/s", "frac": achieved / LDS_ATOMIC_PEAK_TOPS, "launch_ms": launch_ms}}
 
 
-SERVE_BANDS = [(8192.0, 40.0), (8192.0, 110.0), (4096.0, 180.0), (4096.0, 450.0),
-               (2048.0, 330.0), (2048.0, 500.0), (1024.0, 700.0), (1024.0, 950.0)]
+def serve_t_fft(f_lo):
+    """T_FFT of a band by frequency: [20, 128) Hz 8192 s, [128, 256) 4096 s,
+    [256, 512) 2048 s, [512, 1000] 1024 s (every one within the maximum FFT
+    length for which a signal stays within one bin, Table I)."""
+    return 8192.0 if f_lo < 128 else 4096.0 if f_lo < 256 else 2048.0 if f_lo < 512 else 1024.0
 
 
-def serve_bench(ctx, n_req, load, lanes=8, seed=77):
-    """Poisson stream of (band, sky patch, spin-down range) requests through the
-    continuous-batching server; bands are resident 1 Hz peakmaps of a ~149 d
-    run with T_FFT chosen by band."""
-    import numpy as np
+class _BandShape:
+    """What synth.make_grid reads of a peakmap: T_FFT, FFT count, times."""
+
+    def __init__(self, t_fft, t):
+        self.t_fft, self.t, self.n_fft = t_fft, t, int(t.shape[0])
+
+
+def build_serving_bands(ctx, f_lo=20, f_hi=1000, seed=77, t_obs_days=149.0):
+    """Resident 1 Hz peakmaps of every band [f, f + 1) Hz, f = f_lo .. f_hi - 1,
+    of a ~149 d run: Exp(1) equalised spectra drawn on the GPU from a seeded
+    generator over the band and its Doppler and spin-down margins, turned into
+    peakmaps (local maxima above 2.5) by fh_peakmap_from_spectra."""
     import torch
 
     from paper_1407_8333_amd import api, synth
     rng = synth.rng_for(seed)
-    t_obs = 149.0 * 86400.0
-    bands = []
-    for k, (t_fft, f_lo) in enumerate(SERVE_BANDS):
+    t_obs = t_obs_days * 86400.0
+    shapes = {}
+    for t_fft in (8192.0, 4096.0, 2048.0, 1024.0):
         n_fft = int(round(t_obs / (0.5 * t_fft)))
-        m = synth.band_margin_bins(f_lo + 1, t_fft, n_fft, 1e-8)
-        pm = synth.make_noise_peakmap(n_fft, t_fft, int(f_lo * t_fft) - m, int((f_lo + 1) * t_fft) + m,
-                                      seed=seed + k)
-        bands.append((pm, f_lo, ctx.upload(pm)))
+        t = synth.fft_times(n_fft, t_fft)
+        shapes[t_fft] = (_BandShape(t_fft, t), synth.detector_velocity(t, rng))
+    plan = []
+    for f in range(f_lo, f_hi):
+        t_fft = serve_t_fft(f)
+        n_fft = shapes[t_fft][0].n_fft
+        m = synth.band_margin_bins(f + 1.0, t_fft, n_fft, 1e-8)
+        k_lo, k_hi = int(f * t_fft) - m, int((f + 1) * t_fft) + m
+        plan.append((f, t_fft, n_fft, k_lo, k_hi))
+    cap = max(n * (k_hi - k_lo + 2) for _, _, n, k_lo, k_hi in plan)
+    buf = torch.empty(cap, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    bands = []
+    for f, t_fft, n_fft, k_lo, k_hi in plan:
+        nb = k_hi - k_lo + 2  # one guard bin each side
+        sp = buf[:n_fft * nb].view(n_fft, nb)
+        sp.exponential_(generator=gen)
+        shape, v = shapes[t_fft]
+        dpm = api.DevicePeakmap.from_spectra(ctx, sp, k_lo - 1, 2.5, shape.t, v, t_fft)
+        bands.append((shape, float(f), dpm))
+    del buf
+    torch.cuda.synchronize()
+    return bands
+
+
+def serve_bench(ctx, n_req, load, lanes=8, seed=77, burst_n=192):
+    """Poisson stream of (band, sky patch, spin-down range) requests through the
+    continuous-batching server.  Bands: one of the 980 resident 1 Hz bands of
+    20-1000 Hz, uniformly; sky patch: 1-256 random directions, log-uniform in
+    the count; spin-down range: [-1e-9, 1e-10] or [-1e-8, 1e-9] Hz/s, equally
+    likely.  Capacity is measured on a burst submitted at once; the stream then
+    arrives at `load` times that capacity."""
+    import numpy as np
+    import torch
+
+    from paper_1407_8333_amd import api, synth
+    t_build = time.perf_counter()
+    bands = build_serving_bands(ctx, seed=seed)
+    build_s = time.perf_counter() - t_build
+    rng = synth.rng_for(seed + 1)
     ranges = [(-1e-9, 1e-10), (-1e-8, 1e-9)]
 
     def draw():
-        pm, f_lo, dpm = bands[int(rng.integers(len(bands)))]
-        grid = synth.make_grid(pm, f_lo, f_lo + 1.0, *ranges[int(rng.integers(2))])
-        sel = synth.Selection(width=int(round(0.1 * grid.kf * pm.t_fft)))
-        sky = synth.sky_uniform(int(rng.integers(1, 257)), rng)
-        return dpm, grid, sel, sky
+        shape, f_lo, dpm = bands[int(rng.integers(len(bands)))]
+        grid = synth.make_grid(shape, f_lo, f_lo + 1.0, *ranges[int(rng.integers(2))])
+        sel = synth.Selection(width=int(round(0.1 * grid.kf * shape.t_fft)))
+        n_sky = int(min(256, max(1, round(2.0 ** rng.uniform(0.0, 8.0)))))
+        return dpm, grid, sel, synth.sky_uniform(n_sky, rng)
+
+    def out_for(r):
+        return torch.empty((len(r[3]), api.n_subbands(r[1], r[2]), 2, 8), dtype=torch.int32, device="cuda")
+
+    # one search per distinct shape first (T_FFT x spin-down range): tile autotuning
+    for t_fft in (8192.0, 4096.0, 2048.0, 1024.0):
+        shape, f_lo, dpm = next(b for b in bands if b[0].t_fft == t_fft)
+        for rg in ranges:
+            grid = synth.make_grid(shape, f_lo, f_lo + 1.0, *rg)
+            sel = synth.Selection(width=int(round(0.1 * grid.kf * t_fft)))
+            api.fh_hough_candidates(ctx, dpm, synth.sky_uniform(16, rng), grid, sel)
+    torch.cuda.synchronize()
 
     srv = api.Server(ctx, hbm_budget=64 << 30, lanes=lanes)
-    # capacity: a burst of requests submitted at once (96, so that the ramp-down
-    # of the last requests, when lanes fall idle, is a small part of the burst)
-    burst = [draw() for _ in range(96)]
-    outs = [torch.empty((len(b[3]), api.n_subbands(b[1], b[2]), 2, 8), dtype=torch.int32,
-                        device="cuda") for b in burst]
-    for b, o in zip(burst, outs):  # first use of each shape: tile autotuning, allocation
-        api.fh_hough_candidates(ctx, b[0], b[3], b[1], b[2], out=o)
-    torch.cuda.synchronize()
+    # capacity: a burst submitted at once
+    burst = [draw() for _ in range(burst_n)]
+    outs = [out_for(b) for b in burst]
     t0 = time.perf_counter()
     for b, o in zip(burst, outs):
         srv.submit(b[0], b[3], b[1], b[2], o)
@@ -275,8 +332,7 @@ def serve_bench(ctx, n_req, load, lanes=8, seed=77):
     cap = len(burst) / burst_s
     rate = load * cap
     reqs = [draw() for _ in range(n_req)]
-    outs = [torch.empty((len(r[3]), api.n_subbands(r[1], r[2]), 2, 8), dtype=torch.int32,
-                        device="cuda") for r in reqs]
+    outs = [out_for(r) for r in reqs]
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     done = []
     t0 = time.perf_counter()
@@ -292,16 +348,23 @@ def serve_bench(ctx, n_req, load, lanes=8, seed=77):
     srv.close()
     for _, _, d in bands:
         d.release()
+    bad = sum(1 for c in done if c["status"] != 0)
     lat = [c["latency_ms"] for c in done]
+    dev = [c["device_ms"] for c in done]
     cells = sum(c["cell_updates"] for c in done)
-    return {"requests": n_req, "lanes": lanes, "hbm_budget_gib": 64,
+    return {"requests": n_req, "failed": bad, "lanes": lanes, "hbm_budget_gib": 64,
             "arrival_rate_per_s": rate, "capacity_per_s": cap, "load": load,
-            "capacity_throughput": burst_cells / burst_s,
+            "capacity_throughput": burst_cells / burst_s, "burst_requests": burst_n,
             "p50_latency_ms": pct(lat, 50), "p99_latency_ms": pct(lat, 99),
             "mean_queue_ms": float(np.mean([c["queue_ms"] for c in done])),
-            "throughput": cells / wall, "unit": "cell-updates/s",
-            "bands": ["T_FFT %d s at %g-%g Hz" % (t, f, f + 1) for t, f in SERVE_BANDS],
-            "sky_patch": "1-256 random directions", "spin_down_ranges": ranges}
+            "p50_device_ms": pct(dev, 50), "p99_device_ms": pct(dev, 99),
+            # mean number of requests on the device at once (device time / wall)
+            "mean_requests_on_device": float(sum(dev)) / (wall * 1e3),
+            "throughput": cells / wall, "unit": "cell-updates/s", "stream_s": wall,
+            "bands": "980 resident 1 Hz bands, 20-1000 Hz (T_FFT 8192 / 4096 / 2048 / 1024 s "
+                     "below 128 / 256 / 512 / 1000 Hz), ~149 d, built on the GPU in %.1f s" % build_s,
+            "sky_patch": "1-256 random directions, log-uniform count",
+            "spin_down_ranges": ranges}
 
 
 def main():
@@ -314,6 +377,13 @@ def main():
     import torch
 
     from paper_1407_8333_amd import api, synth
+
+    if args.serve_only:
+        ctx = api.Context(0)
+        out = {"serving": serve_bench(ctx, args.serve_requests, args.serve_load, lanes=args.serve_lanes)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
 
     n_sky = args.n_sky or (1024 if args.workload == "batch-256hz" else
                            (4096 if args.workload == "large-1024hz" else 1))
@@ -469,7 +539,7 @@ def main():
         dpm = None
         res["large_band"] = large_band_leg(ctx, args.large_sky)
     if args.serve_requests > 0:
-        res["serving"] = serve_bench(ctx, args.serve_requests, args.serve_load)
+        res["serving"] = serve_bench(ctx, args.serve_requests, args.serve_load, lanes=args.serve_lanes)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
     if dpm is not None:

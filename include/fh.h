@@ -399,12 +399,15 @@ fh_status fh_veto_bins(fh_ctx *ctx, const fh_peakmap *pm, int32_t k_lo, int32_t 
 /* A continuous-batching request server over one context.  Requests
  * (band = a resident peakmap + grid, sky patch, spin-down range) queue on the
  * host; fh_server_poll admits queued requests in arrival order whenever a lane
- * (a HIP stream with its own workspace) is free and the HBM footprint of the
- * work in flight plus the request's fits the budget, launches them, and
- * returns finished ones.  Admitted requests run concurrently on separate
- * streams, so requests that arrive while others are on the GPU overlap with
- * them.  Results are identical to running each request alone with
- * fh_hough_candidates (same kernels, same integer arithmetic).
+ * (a HIP stream) is free and a block of the request's HBM footprint is free in
+ * the server's arena, launches them, and returns finished ones.  The arena
+ * is hbm_budget bytes of device memory allocated once by fh_server_create;
+ * each running request's workspace is a block of it, returned when the
+ * request finishes, so admission never allocates or frees device memory and
+ * the server holds exactly the budget.  Admitted requests run concurrently on
+ * separate streams, so requests that arrive while others are on the GPU
+ * overlap with them.  Results are identical to running each request alone
+ * with fh_hough_candidates (same kernels, same integer arithmetic).
  * All server calls must come from the thread that owns the context. */
 typedef struct fh_server fh_server;
 
@@ -433,14 +436,17 @@ typedef struct {
     int64_t cell_updates;
 } fh_completion;
 
-/* hbm_budget: bytes of workspace that in-flight requests may use together;
- * lanes: concurrent requests (streams), 1 .. 16; max_queue: pending requests
- * accepted before fh_server_submit returns FH_E_BUSY. */
+/* hbm_budget: bytes of the device arena that in-flight requests share (rounded
+ * down to 256; FH_E_NOMEM if it cannot be allocated); lanes: concurrent
+ * requests (streams), 1 .. 16; max_queue: pending requests accepted before
+ * fh_server_submit returns FH_E_BUSY. */
 fh_status fh_server_create(fh_ctx *ctx, int64_t hbm_budget, int32_t lanes, int32_t max_queue,
                            fh_server **out);
 
-/* Validate and queue a request; *id receives its id.  FH_E_BUSY when the
- * queue is full; FH_E_UNSUPPORTED when the request alone exceeds the budget. */
+/* Validate and queue a request; *id receives its id.  Its directions run in
+ * chunks sized so that one chunk's workspace fits budget / lanes where it
+ * can.  FH_E_BUSY when the queue is full; FH_E_UNSUPPORTED when the request's
+ * workspace for one direction at a time exceeds the budget. */
 fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id);
 
 /* Make progress (retire finished lanes, admit and launch queued requests) and

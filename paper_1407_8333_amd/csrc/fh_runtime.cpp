@@ -1467,12 +1467,98 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
+// Byte layout of one search's workspace inside a block of the server's
+// arena: the same buffers ensure_workspace provides, 256-byte aligned.
+struct SearchLayout {
+    size_t gsh = 0, y = 0, y64 = 0, win = 0, wsort = 0, colmax = 0, wq = 0, ws = 0, sky = 0, qctr = 0, total = 0;
+};
+
+SearchLayout search_layout(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
+                           int n_sky, bool weighted) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t N = (size_t)pm->n_fft, c = (size_t)chunk;
+    const size_t ys = (size_t)y_stride(pm->n_peaks, pm->n_fft);
+    const size_t wins = (size_t)8 * c * p.nrbg * p.nbb * win_stride(pm->n_fft);
+    SearchLayout L;
+    size_t o = 0;
+    L.gsh = o;    o += al(8 * N * p.nsp);
+    L.y = o;      o += al(4 * ys * c);
+    L.y64 = o;    if (needs_full_edges(ctx, pm)) o += al(8 * ys * c);
+    L.win = o;    o += al(wins);
+    L.wsort = o;  o += al(wins);
+    L.colmax = o; o += al(8 * c * (size_t)g->nf);
+    L.wq = o;     o += al(weighted ? 4 * c * N : 4);
+    L.ws = o;     o += al(sizeof(WeightStats) * c);
+    L.sky = o;    o += al(24 * (size_t)n_sky);
+    L.qctr = o;   o += al(4 * kXcds);
+    L.total = o;
+    return L;
+}
+
+ChunkBufs carve(char *base, const SearchLayout &L, int32_t *err) {
+    ChunkBufs b{};
+    b.gsh = reinterpret_cast<int64_t *>(base + L.gsh);
+    b.Y = reinterpret_cast<uint32_t *>(base + L.y);
+    b.Y64 = reinterpret_cast<int64_t *>(base + L.y64);
+    b.win = reinterpret_cast<int2 *>(base + L.win);
+    b.wsort = reinterpret_cast<int2 *>(base + L.wsort);
+    b.colmax = reinterpret_cast<unsigned long long *>(base + L.colmax);
+    b.wq = reinterpret_cast<uint32_t *>(base + L.wq);
+    b.ws = reinterpret_cast<WeightStats *>(base + L.ws);
+    b.sky = reinterpret_cast<double *>(base + L.sky);
+    b.qctr = reinterpret_cast<int32_t *>(base + L.qctr);
+    b.err = err;
+    return b;
+}
+
+// First-fit allocator over the server's device arena (host bookkeeping
+// only; block sizes are multiples of 256 bytes).
+struct Arena {
+    char *base = nullptr;
+    size_t bytes = 0;
+    std::map<size_t, size_t> free_;  // offset -> size, never adjacent
+    void reset(char *p, size_t n) {
+        base = p;
+        bytes = n;
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t n, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, o2 = it->first + n;
+            free_.erase(it);
+            if (rest) free_[o2] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + n == nx->first) {  // merge with the next block
+            n += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {  // merge with the previous block
+                pv->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+};
+
 struct ServerRequest {
     uint64_t id = 0;
     fh_request r{};
     std::vector<double> sky;
     Clock::time_point t_submit, t_admit;
+    SearchLayout layout;
     int64_t footprint = 0;
+    size_t arena_off = 0;
     int32_t chunk = 1;
     int32_t W = 64;
     int32_t lane = -1;
@@ -1482,25 +1568,16 @@ struct ServerRequest {
 
 struct Lane {
     hipStream_t st = nullptr;
-    Workspace ws;
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
     uint64_t req = 0;  // 0 = idle
 };
-
-// Workspace bytes of one search of `chunk` directions with plan p.
-int64_t search_footprint(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
-                         int n_sky) {
-    const int64_t N = pm->n_fft;
-    const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(N) +
-                            8 * (int64_t)g->nf + 4 * N + 4 * p.tiles_per_sky + sizeof(WeightStats);
-    return 8 * N * p.nsp + 128 + 24 * (int64_t)n_sky + per_sky * chunk + 4 * (kXcds * 2 + 1);
-}
 
 }  // namespace
 
 struct fh_server {
     fh_ctx *ctx = nullptr;
     int64_t budget = 0;
+    Arena arena;  // budget bytes of device memory, allocated once at creation
     int32_t max_queue = 0;
     std::vector<Lane> lanes;
     std::deque<uint64_t> queue;
@@ -1527,6 +1604,7 @@ void retire_lanes(fh_server *srv) {
             if (hipEventElapsedTime(&ms, L.ev_start, L.ev_done) == hipSuccess) R.device_ms = ms;
         }
         R.latency_ms = ms_between(R.t_submit, now);
+        srv->arena.release(R.arena_off, (size_t)R.footprint);
         srv->in_flight -= R.footprint;
         srv->finished.push_back(R.id);
         L.req = 0;
@@ -1538,29 +1616,31 @@ void admit(fh_server *srv) {
     while (!srv->queue.empty()) {
         const uint64_t id = srv->queue.front();
         ServerRequest &R = srv->reqs[id];
-        if (srv->in_flight + R.footprint > srv->budget) break;  // arrival order: wait for memory
         int li = -1;
         for (size_t k = 0; k < srv->lanes.size(); ++k)
             if (!srv->lanes[k].req) { li = (int)k; break; }
         if (li < 0) break;  // wait for a lane
+        // arrival order: the head waits until a block of its footprint is free
+        size_t off = 0;
+        if (!srv->arena.alloc((size_t)R.footprint, &off)) break;
         srv->queue.pop_front();
         Lane &L = srv->lanes[li];
         R.lane = li;
+        R.arena_off = off;
         R.t_admit = Clock::now();
         R.queue_ms = ms_between(R.t_submit, R.t_admit);
         const fh_request &q = R.r;
         const Plan p = make_plan(q.grid, R.W);
-        const bool weighted = q.d_w != nullptr;
-        ctx->cur = &L.ws;
-        ChunkBufs b;
-        fh_status s = ensure_workspace(ctx, q.pm, &q.grid, p, R.chunk, q.n_sky, weighted, L.st, b);
-        if (!s) s = upload_sky(ctx, R.sky.data(), q.n_sky, b, L.st);
+        // the workspace is the arena block: nothing is allocated or freed here
+        ChunkBufs b = carve(srv->arena.base + off, R.layout, (int32_t *)ctx->err.ptr);
+        fh_status s = FH_OK;
+        if (hipMemcpyAsync(b.sky, R.sky.data(), (size_t)24 * q.n_sky, hipMemcpyHostToDevice, L.st) != hipSuccess)
+            s = fail(FH_E_DEVICE, "copying the request's sky vectors failed");
         if (!s && hipEventRecord(L.ev_start, L.st) != hipSuccess) s = fail(FH_E_DEVICE, "hipEventRecord");
         if (!s)
             s = run_search(ctx, q.pm, &q.grid, p, R.chunk, q.n_sky, q.d_w, q.w_stride,
                            FH_SCHED_PERSISTENT, &q.sel, q.d_out, b, L.st);
         if (hipEventRecord(L.ev_done, L.st) != hipSuccess && !s) s = fail(FH_E_DEVICE, "hipEventRecord");
-        ctx->cur = &ctx->main_ws;
         R.status = s;
         srv->in_flight += R.footprint;
         L.req = id;
@@ -1580,9 +1660,16 @@ fh_status fh_server_create(fh_ctx *ctx, int64_t hbm_budget, int32_t lanes, int32
     if (hbm_budget <= 0) return fail(FH_E_INVALID, "hbm_budget must be > 0");
     if (lanes < 1 || lanes > 16) return fail(FH_E_INVALID, "lanes=%d outside 1..16", lanes);
     if (max_queue < 1) return fail(FH_E_INVALID, "max_queue must be >= 1");
+    // the arena is carved in 256-byte pieces
+    const int64_t budget = hbm_budget / 256 * 256;
+    if (budget <= 0) return fail(FH_E_INVALID, "hbm_budget must be at least 256 bytes");
+    void *mem = nullptr;
+    if (hipMalloc(&mem, (size_t)budget) != hipSuccess)
+        return fail(FH_E_NOMEM, "allocating the server's %lld-byte arena failed", (long long)budget);
     fh_server *srv = new fh_server();
     srv->ctx = ctx;
-    srv->budget = hbm_budget;
+    srv->budget = budget;
+    srv->arena.reset(static_cast<char *>(mem), (size_t)budget);
     srv->max_queue = max_queue;
     srv->lanes.resize(lanes);
     for (Lane &L : srv->lanes) {
@@ -1622,11 +1709,15 @@ fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id) 
     R.W = choose_tile_bins(ctx, req->pm, &req->grid, 0, req->d_w != nullptr);
     const Plan p = make_plan(req->grid, R.W);
     // the largest chunk whose footprint fits one lane's share of the budget
+    const bool weighted = req->d_w != nullptr;
     const int64_t share = srv->budget / (int64_t)srv->lanes.size();
     int chunk = std::min<int>(req->n_sky, 256);
-    while (chunk > 1 && search_footprint(ctx, req->pm, &req->grid, p, chunk, req->n_sky) > share) chunk = (chunk + 1) / 2;
+    while (chunk > 1 &&
+           (int64_t)search_layout(ctx, req->pm, &req->grid, p, chunk, req->n_sky, weighted).total > share)
+        chunk = (chunk + 1) / 2;
     R.chunk = chunk;
-    R.footprint = search_footprint(ctx, req->pm, &req->grid, p, chunk, req->n_sky);
+    R.layout = search_layout(ctx, req->pm, &req->grid, p, chunk, req->n_sky, weighted);
+    R.footprint = (int64_t)R.layout.total;
     if (R.footprint > srv->budget) {
         srv->next_id--;
         return fail(FH_E_UNSUPPORTED, "request needs %lld workspace bytes, over the %lld-byte budget",
@@ -1721,11 +1812,11 @@ void fh_server_destroy(fh_server *srv) {
     fh_server_drain(srv);
     for (Lane &L : srv->lanes) {
         if (L.st) (void)hipStreamSynchronize(L.st);
-        L.ws.release();
         if (L.ev_start) (void)hipEventDestroy(L.ev_start);
         if (L.ev_done) (void)hipEventDestroy(L.ev_done);
         if (L.st) (void)hipStreamDestroy(L.st);
     }
+    if (srv->arena.base) (void)hipFree(srv->arena.base);
     delete srv;
 }
 

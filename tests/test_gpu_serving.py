@@ -1,11 +1,46 @@
 """Continuous-batching server: each request's candidates are identical alone
-and in the mix; admission respects the HBM budget; queued requests cancel."""
+and in the mix and match the oracle on sampled directions; admission respects
+the HBM budget (the arena holds the workspaces of the running requests);
+queued requests cancel."""
+import math
+
 import numpy as np
 import pytest
 
+import oracle
 from paper_1407_8333_amd import synth
 
 pytestmark = pytest.mark.gpu
+REL_TOL = 1e-5
+
+
+def _check_against_oracle(dec, s, pm, grid, sel, nhat, weights=None):
+    """Candidates of direction s of a served request against the oracle's map:
+    bit-exact unweighted; weighted within 1e-5 max(|H|, mean w), CR included."""
+    w64 = None if weights is None else np.asarray(weights, np.float64)
+    m = oracle.hough_map(pm, grid, nhat, weights=w64)
+    idx, val = oracle.candidates(m, sel.width, sel.excl, sel.sep)
+    q = oracle.p0(sel.theta)
+    for sb in range(idx.shape[0]):
+        for r in range(2):
+            valid = int(dec["valid"][s, sb, r])
+            assert valid == idx[sb, r, 0], (s, sb, r)
+            if not valid:
+                continue
+            if w64 is None:
+                assert (dec["bin"][s, sb, r], dec["row"][s, sb, r]) == (idx[sb, r, 1], idx[sb, r, 2])
+                assert dec["value"][s, sb, r] == val[sb, r]
+                cr = float(oracle.critical_ratio(val[sb, r], pm.n_fft, sel.theta))
+                assert dec["cr"][s, sb, r] == pytest.approx(cr, rel=1e-5, abs=1e-5)
+            else:
+                b, row = int(dec["bin"][s, sb, r]), int(dec["row"][s, sb, r])
+                tol = REL_TOL * max(val[sb, r], float(np.mean(w64)))
+                assert m[row, b] >= val[sb, r] - 2 * tol
+                assert dec["value"][s, sb, r] == pytest.approx(val[sb, r], abs=2 * tol)
+                ws, w2 = float(w64.sum()), float((w64 * w64).sum())
+                cr = float(oracle.critical_ratio_weighted(val[sb, r], ws, w2, sel.theta))
+                sigma = math.sqrt(q * (1 - q) * w2)
+                assert abs(float(dec["cr"][s, sb, r]) - cr) <= 2 * tol / sigma + 1e-5 * (1 + abs(cr))
 
 
 def _band(seed, t_fft, f_lo, n_fft):
@@ -79,6 +114,56 @@ def test_alone_equals_mix(setup):
         assert done[k]["status"] == 0
         assert done[k]["latency_ms"] >= done[k]["queue_ms"] >= 0
         assert torch.equal(outs[k], alone[k]), k
+    # every served request against the oracle on its first and last direction
+    wts_host = [w.cpu().numpy() for w in wts]
+    for k, (bi, grid, sel, sky, weighted) in enumerate(reqs):
+        dec = api.decode_candidates(outs[k])
+        for s in sorted({0, len(sky) - 1}):
+            _check_against_oracle(dec, s, bands[bi], grid, sel, sky[s],
+                                  weights=wts_host[bi] if weighted else None)
+
+
+def test_arena_admits_by_footprint(setup):
+    """Two lanes but an arena that holds one request's workspace (each request
+    runs its directions one at a time, the smallest chunk): the second request
+    waits for memory, not for a lane, and both finish with the results of the
+    request run alone."""
+    import torch
+    from paper_1407_8333_amd import api
+    ctx, bands, dpms = setup
+    pm = bands[2]
+    f_lo = pm.k_lo / pm.t_fft + 0.01
+    grid = synth.make_grid(pm, f_lo, f_lo + 0.2, -1e-8, 1e-9)
+    sel = synth.Selection(width=512)
+    sky = synth.sky_uniform(6, synth.rng_for(12))
+    ref = api.fh_hough_candidates(ctx, dpms[2], sky, grid, sel)
+    one = torch.empty((1, api.n_subbands(grid, sel), 2, 8), dtype=torch.int32, device="cuda")
+    big = api.Server(ctx, hbm_budget=1 << 30, lanes=2)
+    big.submit(dpms[2], sky[:1], grid, sel, one, tag=0)
+    big.drain()
+    (c0,) = big.poll()
+    big.close()
+    f1 = int(c0["footprint"])  # workspace of a one-direction chunk
+    assert 0 < f1 < (1 << 30)
+    budget = f1 + f1 // 2
+    srv = api.Server(ctx, hbm_budget=budget, lanes=2)
+    outs = [torch.full_like(ref, -7) for _ in range(2)]
+    srv.submit(dpms[2], sky, grid, sel, outs[0], tag=1)
+    srv.submit(dpms[2], sky, grid, sel, outs[1], tag=2)
+    done = {c["tag"]: c for c in srv.poll()}  # admits what fits
+    st = srv.stats()
+    assert st["running"] + len(done) == 1 and st["queued"] == 1, st
+    assert 0 < st["bytes_in_flight"] <= budget
+    for _ in range(100000):
+        for c in srv.poll():
+            done[c["tag"]] = c
+        if len(done) == 2:
+            break
+    srv.close()
+    assert done[1]["status"] == 0 and done[2]["status"] == 0
+    assert done[1]["footprint"] == f1 and done[2]["footprint"] == f1
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], ref) and torch.equal(outs[1], ref)
 
 
 def test_budget_admission_and_cancel(setup):
