@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream (for device traces of the lanes)")
     ap.add_argument("--serve-lanes", type=int, default=8)
+    ap.add_argument("--overlap-from", default=None,
+                    help="print the stream overlap of a rocprofv3 kernel_trace.csv and exit")
+    ap.add_argument("--overlap-skip", nargs="*", default=[],
+                    help="stream ids left out of --overlap-from (e.g. the input-building stream)")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the Poisson serving run (0 disables it)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -367,8 +371,53 @@ def serve_bench(ctx, n_req, load, lanes=8, seed=77, burst_n=192):
             "spin_down_ranges": ranges}
 
 
+def trace_overlap(path, skip=()):
+    """Overlap of kernels from different streams in a rocprofv3 kernel trace
+    (kernel_trace.csv): the time during which kernels of two or more streams
+    (Stream_Id, else Queue_Id) run at once, against the time any kernel runs.
+    Streams in `skip` (e.g. the one that built the inputs) are left out."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    key = "Stream_Id" if rows and "Stream_Id" in rows[0] else "Queue_Id"
+    rows = [r for r in rows if r[key] not in set(skip)]
+    ev = []
+    for r in rows:
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        tile = "k_tiles" in r["Kernel_Name"]
+        ev.append((a, 1, r[key], tile))
+        ev.append((b, -1, r[key], tile))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active, tiles = {}, {}
+    busy = multi = multi_tiles = 0
+    last = ev[0][0] if ev else 0
+    for t, d, q, tile in ev:
+        dt = t - last
+        if active:
+            busy += dt
+        if len(active) >= 2:
+            multi += dt
+        if len(tiles) >= 2:
+            multi_tiles += dt
+        last = t
+        active[q] = active.get(q, 0) + d
+        if active[q] == 0:
+            del active[q]
+        if tile:
+            tiles[q] = tiles.get(q, 0) + d
+            if tiles[q] == 0:
+                del tiles[q]
+    return {"kernels": len(rows), "streams": sorted({r[key] for r in rows}), "stream_key": key,
+            "queues": sorted({r["Queue_Id"] for r in rows}), "skipped_streams": sorted(skip),
+            "busy_ms": busy * 1e-6, "two_or_more_streams_ms": multi * 1e-6,
+            "two_or_more_streams_frac": multi / busy if busy else 0.0,
+            "tile_kernels_of_two_or_more_streams_ms": multi_tiles * 1e-6}
+
+
 def main():
     args = parse()
+    if args.overlap_from:
+        print(json.dumps(trace_overlap(args.overlap_from, args.overlap_skip)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the frequency-Hough path on a "
               "single MI355X (no multi-GPU code path); run with --gpus 1", file=sys.stderr)

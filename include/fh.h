@@ -27,8 +27,8 @@
  *   Rejected with FH_E_UNSUPPORTED: a grid whose largest step
  *   |dfdot tau_i| K_f T_FFT reaches 128 fine bins per row (the tiles keep
  *   tile-relative stripe edges in 32 bits), a peakmap with an FFT of 65536
- *   peaks or more, and n_fft * (ns rounded up to 16) reaching 2^28 (the
- *   per-row shift table is addressed with 31-bit byte offsets).
+ *   peaks or more, and n_fft * ceil(ns / 16) reaching 2^28 (the per-row
+ *   shift records are addressed with 31-bit byte offsets).
  *
  * Conventions
  *   - Every pointer named d_* is device memory on the context's device and is
@@ -156,7 +156,9 @@ void fh_ctx_destroy(fh_ctx *ctx);
 
 /* Synchronise `stream` and report (then clear) the device-side error flag:
  * FH_E_INVALID if a weight vector used since the last check held a value that
- * is not finite or outside (0, 65536). */
+ * is not finite or outside (0, 65536); FH_E_DEVICE if a per-row spin-down
+ * residual left its 2-bit code (excluded by the shifts' error bound; a
+ * broken invariant, not an input error). */
 fh_status fh_ctx_check(fh_ctx *ctx, void *stream);
 
 /* Tuning knobs of a context, for experiments and tests.  Results never
@@ -247,8 +249,9 @@ fh_status fh_hough_map_f32(fh_ctx *ctx, const fh_peakmap *pm, const double nhat[
  * until the process ends; the array's address on each device is taken when
  * the first context on that device is created.  A map needing more than
  * 64 MiB is rejected with FH_E_UNSUPPORTED before anything is enqueued: the
- * need is about 8 n_fft ceil16(ns) + 4 (n_peaks + 16 n_fft) + 16 x (row groups
- * of 64 rows) x (tiles along the band) x (n_fft rounded up to 192) bytes.
+ * need is about 4 (n_peaks + 16 n_fft) + 16 x (row groups of 64 rows) x (tiles
+ * along the band) x (n_fft rounded up to 192) + 8 n_fft ceil(ns / 16) +
+ * 80 n_fft bytes.
  * Every call on a GPU shares that GPU's array and leaves its contents there:
  * calls that overlap on one GPU (different streams or contexts without
  * ordering) race, so serialise them, e.g. on one stream. */

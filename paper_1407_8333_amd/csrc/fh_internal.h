@@ -59,8 +59,8 @@ struct TileArgs {
     int32_t n_slots;              // sky directions in this chunk
     const uint32_t *Y;            // [slot][P] low words of the stripe edges (2^-16 fine bins)
     const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] sorted windows
-    const int64_t *gsh;           // [N][nsp] spin-down shifts G_is (2^-16 fine bins)
-    int32_t nsp;                  // rows of the shift table: nrb * 16
+    const uint2 *rec;             // [nrb][N] low word of G_{i,s0} and the rows' residual codes
+    const uint32_t *step;         // [N][16] floor(j q_i / 2^16): the rows' linear steps
     const uint32_t *wq;           // [slot][N] fixed-point weights or nullptr
     const WeightStats *ws;        // [slot * ws_stride] or nullptr
     int32_t ws_stride;            // 0: one shared weight vector, 1: one per slot
@@ -77,9 +77,12 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 // p[0..2] = (x, y, z), written by a kernel (no copy from host memory)
 hipError_t launch_set_f64x3(double *p, double x, double y, double z, hipStream_t st);
-// G[i][s] = rint(((fdot0 + s dfdot) (t_i - t0)) (K_f T_FFT) 2^16), s < nsp
-hipError_t launch_row_shifts(int32_t n_fft, int32_t nsp, const double *t, double t0, double t_fft, int32_t kf,
-                             double fdot0, double dfdot, int64_t *gsh, hipStream_t st);
+// spin-down shift tables of G_is = rint(((fdot0 + s dfdot) (t_i - t0)) (K_f T_FFT) 2^16):
+// gwin [N][nrbg][2] (first and last grid row of each row group), rec [nrb][N],
+// step [N][16] (see k_shift_tables); err bit 2 if a residual code overflows
+hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *t, double t0, double t_fft,
+                               int32_t kf, double fdot0, double dfdot, int64_t *gwin, uint2 *rec, uint32_t *step,
+                               int32_t *err, hipStream_t st);
 hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
                                int32_t mult, WeightStats *ws, int32_t *err_flag, hipStream_t st);
 hipError_t launch_prep(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
@@ -98,7 +101,7 @@ constexpr int kFrontMaxF = 16;
 int front_ffts_per_block(int32_t max_per_fft);
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                         const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                        const int64_t *gsh, int32_t nsp, uint32_t *Y, const float *w,
+                        const int64_t *gwin, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
                         int2 *win, int32_t shift_mode, double q, hipStream_t st);
@@ -109,7 +112,7 @@ hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t
                                int2 *wsorted, hipStream_t st);
 // method 0: two binary searches per entry; 1: one sweep per FFT
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
-                          const int64_t *gsh, int32_t nsp, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+                          const int64_t *gwin, int32_t nrbg, int32_t nbb, int32_t W,
                           int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st);
 hipError_t launch_tiles(const TileArgs &a, bool weighted, bool want_map, bool want_colmax,
                         bool persistent, int32_t n_tiles, int32_t grid_blocks, hipStream_t st);

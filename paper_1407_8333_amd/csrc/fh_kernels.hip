@@ -1,8 +1,8 @@
 // HIP kernels of the frequency-Hough (FH) library for gfx950 (MI355X).
 //
 // Pipeline for one chunk of sky directions (Sec. "Frequency-Hough transform"):
-//   k_row_shifts   per (FFT, spin-down row): the row's shift G_is in 2^-16
-//                  fine bins (Eqs. uno, sdstep).              sky independent
+//   k_shift_tables per (FFT, row block): the rows' shifts G_is in 2^-16 fine
+//                  bins (Eqs. uno, sdstep) as compact tables.  sky independent
 //   k_weight_stats per weight vector: sum w, sum w^2, fixed-point bits F.
 //   k_prep         per (sky, peak): Doppler-corrected stripe edge Y (Eq.
 //                  fdopp, Eq. due) and per (sky, FFT) fixed-point weights.
@@ -78,23 +78,61 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
 // spin-down shifts (Eqs. uno, sdstep): row s has the spin-down
 // fdot_s = fdot0 + s dfdot, and FFT i's stripes in that row are shifted by
 //   G_is = rint((fdot_s tau_i) S),  tau_i = t_i - t0,  S = (K_f T_FFT) kQ
-// rounded once per row.  The table G[i][s] covers s < nsp (every row of the
-// padded row blocks; rows past the grid are computed by the same formula and
-// never reach the output).
+// rounded once per row (rows past the grid, up to the end of the last row
+// block, follow the same formula and never reach the output).
 
-__global__ void k_row_shifts(int32_t n_fft, int32_t nsp, const double *__restrict__ t, double t0,
-                             double S, double fdot0, double dfdot, int64_t *__restrict__ gsh) {
-    const int64_t n = (int64_t)n_fft * nsp;
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-         x += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = x / nsp;
-        const int32_t s = (int32_t)(x - i * nsp);
+__device__ __forceinline__ int64_t row_shift(double tau, double S, double fdot0, double dfdot, int32_t s) {
+    double fs = (double)s * dfdot;
+    fs = fdot0 + fs;
+    double a = fs * tau;
+    a = a * S;
+    return (int64_t)rint(a);
+}
+
+// The tiles need, for FFT i and the 16 rows s0 + j of a row block, the
+// offsets G_{i,s0} - G_{i,s0+j}.  With q_i = rint(((dfdot tau_i) S) 2^16) the
+// row step in 2^-32 fine bins, floor(j q_i / 2^16) is within (-1, 1] + 1e-3
+// of j's exact step, and each G within 0.5 of its exact value, so
+//   c_ij = G_{i,s0+j} - G_{i,s0} - floor(j q_i / 2^16)  lies in {-1, 0, 1, 2}.
+// Tables (all sky independent):
+//   step[i][j]  = low word of floor(j q_i / 2^16)                  [N][16]
+//   rec[rb][i]  = (low word of G_{i,s0}, sum_j (c_ij + 1) << 2j)   [nrb][N]
+//   gwin[i][g]  = (G_is at the first and at the last grid row of row
+//                 group g), for the peak windows                   [N][nrbg][2]
+// A code outside {-1 .. 2} (impossible by the bound above) sets bit 2 of the
+// error flag.
+__global__ void k_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *__restrict__ t, double t0,
+                               double S, double fdot0, double dfdot, int64_t *__restrict__ gwin,
+                               uint2 *__restrict__ rec, uint32_t *__restrict__ step,
+                               int32_t *__restrict__ err) {
+    const int32_t nrbg = (nrb + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
+    const int64_t n = (int64_t)n_fft * nrb;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t rb = (int32_t)(x / n_fft);
+        const int32_t i = (int32_t)(x - (int64_t)rb * n_fft);
         const double tau = t[i] - t0;
-        double fs = (double)s * dfdot;
-        fs = fdot0 + fs;
-        double a = fs * tau;
-        a = a * S;
-        gsh[x] = (int64_t)rint(a);
+        double sig = dfdot * tau;
+        sig = sig * S;
+        const int64_t q = (int64_t)rint(sig * 65536.0);
+        const int32_t s0 = rb * kTileRows;
+        const int64_t g0 = row_shift(tau, S, fdot0, dfdot, s0);
+        uint32_t codes = 0;
+        bool bad = false;
+        for (int j = 0; j < kTileRows; ++j) {
+            const int64_t lin = ((int64_t)j * q) >> 16;  // floor (arithmetic shift)
+            const int64_t c = row_shift(tau, S, fdot0, dfdot, s0 + j) - g0 - lin;
+            bad = bad || c < -1 || c > 2;
+            codes |= (uint32_t)((c + 1) & 3) << (2 * j);
+            if (rb == 0) step[(int64_t)i * kTileRows + j] = (uint32_t)(uint64_t)lin;
+        }
+        rec[(int64_t)rb * n_fft + i] = make_uint2((uint32_t)(uint64_t)g0, codes);
+        if (bad) atomicOr(err, 2);
+        if (rb % kRowBlocksPerGroup == 0) {
+            const int32_t g = rb / kRowBlocksPerGroup;
+            const int32_t s_hi = min(s0 + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
+            gwin[((int64_t)i * nrbg + g) * 2] = g0;
+            gwin[((int64_t)i * nrbg + g) * 2 + 1] = row_shift(tau, S, fdot0, dfdot, s_hi);
+        }
     }
 }
 
@@ -220,8 +258,8 @@ __global__ void __launch_bounds__(256) k_prep(
 __global__ void __launch_bounds__(256) k_front(
     int32_t n_fft, int64_t n_peaks, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ bins, const double *__restrict__ v,
-    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ gsh,
-    int32_t nsp, uint32_t *__restrict__ Y, const float *__restrict__ w,
+    const double *__restrict__ sky, int32_t kf, int64_t b0, const int64_t *__restrict__ gwin,
+    uint32_t *__restrict__ Y, const float *__restrict__ w,
     int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
     uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
     int2 *__restrict__ win, int32_t shift_mode, double q) {
@@ -311,9 +349,8 @@ __global__ void __launch_bounds__(256) k_front(
         if (f < n_fft) {
             const int64_t p0 = offsets[f] + (int64_t)kYPad * f - pb;
             const int64_t p1 = offsets[f + 1] + (int64_t)kYPad * f - pb;
-            const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
-            const int32_t s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
-            const int64_t q_lo = gsh[(int64_t)f * nsp + s_lo], q_hi = gsh[(int64_t)f * nsp + s_hi];
+            // shifts of the group's first and last grid rows
+            const int64_t q_lo = gwin[((int64_t)f * nrbg + g) * 2], q_hi = gwin[((int64_t)f * nrbg + g) * 2 + 1];
             // max_s a_s = floor((Y - min G) / kQ) >= t  <=>  Y >= t kQ + min G
             // min_s a_s = floor((Y - max G) / kQ) >= t  <=>  Y >= t kQ + max G
             const int64_t y_lo = ((int64_t)jb * W - (kf - 1)) * kQ + (q_lo < q_hi ? q_lo : q_hi);
@@ -344,7 +381,7 @@ __global__ void __launch_bounds__(256) k_front(
 
 __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
                           const int64_t *__restrict__ Y, int64_t n_peaks,
-                          const int64_t *__restrict__ gsh, int32_t nsp, int32_t ns, int32_t nrbg,
+                          const int64_t *__restrict__ gwin, int32_t nrbg,
                           int32_t nbb, int32_t W, int32_t kf, int2 *__restrict__ win) {
     const int32_t n_pad = win_stride(n_fft);
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -357,13 +394,10 @@ __global__ void k_windows(int32_t n_fft, const int64_t *__restrict__ offsets,
         *out = make_int2(0, 0);
         return;
     }
-    const int32_t s_lo = g * kRowBlocksPerGroup * kTileRows;
-    int32_t s_hi = s_lo + kRowBlocksPerGroup * kTileRows - 1;
-    if (s_hi > ns - 1) s_hi = ns - 1;
     const int64_t c0 = (int64_t)jb * W - (kf - 1);
     const int64_t wc = (int64_t)W + kf - 1;
-    const int64_t q_lo = gsh[(int64_t)i * nsp + s_lo] + c0 * kQ;
-    const int64_t q_hi = gsh[(int64_t)i * nsp + s_hi] + c0 * kQ;
+    const int64_t q_lo = gwin[((int64_t)i * nrbg + g) * 2] + c0 * kQ;
+    const int64_t q_hi = gwin[((int64_t)i * nrbg + g) * 2 + 1] + c0 * kQ;
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int64_t p0 = offsets[i] + (int64_t)kYPad * i, p1 = offsets[i + 1] + (int64_t)kYPad * i;
     // lo: first peak whose larger column is >= 0
@@ -403,7 +437,7 @@ __device__ __forceinline__ int floor_div_w(int64_t x, int W, float inv_w) {
 
 __global__ void __launch_bounds__(256) k_windows_sweep(
     int32_t n_fft, const int64_t *__restrict__ offsets, const int64_t *__restrict__ Y,
-    int64_t n_peaks, const int64_t *__restrict__ gsh, int32_t nsp, int32_t ns, int32_t nrbg, int32_t nbb,
+    int64_t n_peaks, const int64_t *__restrict__ gwin, int32_t nrbg, int32_t nbb,
     int32_t W, int32_t kf, int2 *__restrict__ win) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -418,13 +452,11 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
     const int64_t *Ys = Y + (int64_t)slot * y_stride(n_peaks, n_fft);
     const int p0 = (int)(offsets[i] + (int64_t)kYPad * i);
     const int p1 = (int)(offsets[i + 1] + (int64_t)kYPad * i);
-    const int64_t *gi = gsh + (int64_t)i * nsp;
+    const int64_t *gi = gwin + (int64_t)i * nrbg * 2;
     const float inv_w = 1.0f / (float)W;
     for (int g = 0; g < nrbg; ++g) {
         int2 *wg = win + ((int64_t)slot * nrbg + g) * nbb * (int64_t)n_pad + i;
-        const int s_lo = g * kRowBlocksPerGroup * kTileRows;
-        const int s_hi = min(s_lo + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
-        const int64_t q_lo = gi[s_lo], q_hi = gi[s_hi];
+        const int64_t q_lo = gi[2 * g], q_hi = gi[2 * g + 1];
         int prev_hi = -1;  // jhi of the peak before this chunk
         int prev_lo = 0;   // jlo of the peak before this chunk
         for (int pb = p0; pb < p1; pb += 64) {
@@ -1019,13 +1051,13 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     const int total = kTileWaves * nblk;  // blocks of a tile
     const int i_last = A.n_fft - 1;
     const int home = blockIdx.x % kXcds;
-    const __amdgpu_buffer_rsrc_t r_g = buf(A.gsh);
-    const uint32_t nsp = (uint32_t)A.nsp;
+    const __amdgpu_buffer_rsrc_t r_rec = buf(A.rec), r_step = buf(A.step);
+    const uint32_t lane_code = 2u * (uint32_t)j;  // bit offset of this row's residual code
 
     // per-tile buffers: window row, stripe edges and weights of the slot
     struct Bufs {
         __amdgpu_buffer_rsrc_t win, y, wq;
-        uint32_t s0;  // first row of the tile
+        uint32_t rb;  // row block of the tile
     };
     auto tile_bufs = [&](int t) {
         int slot, rb, jb;
@@ -1035,8 +1067,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         b.win = buf(A.win + (((int64_t)slot * A.nrbg + g) * A.nbb + jb) * n_pad);
         // low 32 bits of the stripe edges (all the tile needs: see stripe_word)
         b.y = buf(A.Y + (int64_t)slot * y_stride(A.n_peaks, A.n_fft));
-        b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.gsh);
-        b.s0 = (uint32_t)(rb * kTileRows);
+        b.wq = buf(WEIGHTED ? (const void *)(A.wq + (int64_t)slot * A.n_fft) : (const void *)A.step);
+        b.rb = (uint32_t)rb;
         return b;
     };
     // Blocks are handed out dynamically: block g of a tile is block g / 16 of
@@ -1063,15 +1095,17 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     };
     // stripe edges, row terms and weights of block bb (stage 2): the chunk
     // sizes follow the largest window of the four groups, group 0's (the runs
-    // are sorted by window size).  The row terms come from the low words of
-    // the FFT's shifts of rows s0 and s0 + j (the host keeps N nsp below 2^28,
-    // so the byte offsets fit 31 bits).
+    // are sorted by window size).  The row term of row s0 + j,
+    // G_{i,s0} - G_{i,s0+j} = 1 - step[i][j] - code_j (mod 2^32), comes from the
+    // FFT's step table and the row block's record (the host keeps N nrb below
+    // 2^28, so the byte offsets fit 31 bits).
     auto stage_y = [&](Quad &Q, const Bufs &B) {
         Q.cnt = Q.pk & 0xFFFF;
         const uint32_t fc = min((uint32_t)((Q.pk >> 16) * kTileWaves + Q.run), (uint32_t)i_last);
-        const uint32_t go = (fc * nsp + B.s0) * 8u;
-        Q.gb = ld_u32(r_g, go);
-        Q.t = Q.gb - ld_u32(r_g, go + (uint32_t)j * 8u);
+        const auto r = __builtin_amdgcn_raw_buffer_load_b64(r_rec, (B.rb * (uint32_t)A.n_fft + fc) * 8u, 0, 0);
+        Q.gb = (uint32_t)r[0];
+        const uint32_t code = __builtin_amdgcn_ubfe((uint32_t)r[1], lane_code, 2u);
+        Q.t = (1u - ld_u32(r_step, (fc * kTileRows + (uint32_t)j) * 4u)) - code;
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
         Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
@@ -1442,12 +1476,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_shifts(int32_t n_fft, int32_t nsp, const double *t, double t0, double t_fft, int32_t kf,
-                             double fdot0, double dfdot, int64_t *gsh, hipStream_t st) {
-    const int64_t n = (int64_t)n_fft * nsp;
+hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *t, double t0, double t_fft,
+                               int32_t kf, double fdot0, double dfdot, int64_t *gwin, uint2 *rec, uint32_t *step,
+                               int32_t *err, hipStream_t st) {
+    const int64_t n = (int64_t)n_fft * nrb;
     if (n <= 0) return hipSuccess;
     const double S = ((double)kf * t_fft) * kQd;
-    k_row_shifts<<<grid_for(n, 256), 256, 0, st>>>(n_fft, nsp, t, t0, S, fdot0, dfdot, gsh);
+    k_shift_tables<<<grid_for(n, 256), 256, 0, st>>>(n_fft, nrb, ns, t, t0, S, fdot0, dfdot, gwin, rec, step, err);
     return hipGetLastError();
 }
 
@@ -1476,7 +1511,7 @@ int front_ffts_per_block(int32_t max_per_fft) {
 
 hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, const int32_t *bins,
                         const double *v, const double *sky, int32_t n_slots, int32_t kf, int64_t b0,
-                        const int64_t *gsh, int32_t nsp, uint32_t *Y, const float *w,
+                        const int64_t *gwin, uint32_t *Y, const float *w,
                         int32_t w_stride, const WeightStats *ws, int32_t ws_stride, uint32_t *wq,
                         int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F, int32_t max_per_fft,
                         int2 *win, int32_t shift_mode, double q, hipStream_t st) {
@@ -1484,7 +1519,7 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
     dim3 grid(win_stride(n_fft) / F, n_slots);
     const size_t lds = ((size_t)F * (max_per_fft + kYPad) * 8 + 255) / 256 * 256;
     if (F > kFrontMaxF || lds > (size_t)kFrontLdsBytes) return hipErrorInvalidValue;
-    k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, gsh, nsp, Y,
+    k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, gwin, Y,
                                                w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win,
                                                shift_mode, q);
     return hipGetLastError();
@@ -1503,14 +1538,14 @@ hipError_t launch_sort_windows(int32_t n_fft, int32_t nrbg, int32_t nbb, int32_t
 }
 
 hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *Y, int64_t n_peaks,
-                          const int64_t *gsh, int32_t nsp, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W,
+                          const int64_t *gwin, int32_t nrbg, int32_t nbb, int32_t W,
                           int32_t kf, int32_t n_slots, int2 *win, int method, hipStream_t st) {
     if (method == 0) {
         dim3 grid(grid_for((int64_t)nbb * win_stride(n_fft), 256), nrbg, n_slots);
-        k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gsh, nsp, ns, nrbg, nbb, W, kf, win);
+        k_windows<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gwin, nrbg, nbb, W, kf, win);
     } else {
         dim3 grid((win_stride(n_fft) + 3) / 4, n_slots);
-        k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gsh, nsp, ns, nrbg, nbb, W, kf, win);
+        k_windows_sweep<<<grid, 256, 0, st>>>(n_fft, offsets, Y, n_peaks, gwin, nrbg, nbb, W, kf, win);
     }
     return hipGetLastError();
 }

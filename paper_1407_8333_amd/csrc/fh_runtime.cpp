@@ -146,16 +146,16 @@ struct fh_peakmap {
 // Device and pinned buffers of one in-flight search.  A context owns one;
 // each serving lane owns another.
 struct Workspace {
-    DevBuf gsh, Y, Y64, win, wsort, colmax, wq, ws, sky, qctr;
+    DevBuf sht, Y, Y64, win, wsort, colmax, wq, ws, sky, qctr;
     PinnedBuf h_sky;
     size_t device_bytes() const {
         size_t n = 0;
-        for (const DevBuf *b : {&gsh, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (const DevBuf *b : {&sht, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             n += b->bytes;
         return n;
     }
     void release() {
-        for (DevBuf *b : {&gsh, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
+        for (DevBuf *b : {&sht, &Y, &Y64, &win, &wsort, &colmax, &wq, &ws, &sky, &qctr})
             b->release();
         h_sky.release();
     }
@@ -199,15 +199,30 @@ namespace {
 
 struct Plan {
     int W, nrb, nbb, nrbg;
-    int nsp;  // rows of the spin-down shift table (every row of the row blocks)
     int64_t tiles_per_sky;
 };
+
+// Spin-down shift tables of one search (see k_shift_tables), one buffer:
+// gwin int64 [N][nrbg][2] | rec uint2 [nrb][N] | step u32 [N][16].
+struct ShiftLayout {
+    size_t gwin, rec, step, total;
+};
+
+ShiftLayout shift_layout(int64_t n_fft, int nrb, int nrbg) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    ShiftLayout L;
+    size_t o = 0;
+    L.gwin = o; o += al((size_t)16 * n_fft * nrbg);
+    L.rec = o;  o += al((size_t)8 * n_fft * nrb);
+    L.step = o; o += al((size_t)4 * kTileRows * n_fft);
+    L.total = o;
+    return L;
+}
 
 Plan make_plan(const fh_grid &g, int W) {
     Plan p;
     p.W = W;
     p.nrb = (g.ns + kTileRows - 1) / kTileRows;
-    p.nsp = p.nrb * kTileRows;
     p.nbb = (g.nf + W - 1) / W;
     p.nrbg = (p.nrb + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
     p.tiles_per_sky = (int64_t)p.nrb * p.nbb;
@@ -250,10 +265,10 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     if (!(gmax < 1e12)) return fail(FH_E_INVALID, "spin-down shifts exceed the fixed-point range");
     if (pm->max_per_fft >= 65536)
         return fail(FH_E_UNSUPPORTED, "an FFT holds %d peaks; at most 65535 are supported", pm->max_per_fft);
-    // the tiles address the shift table [N][rows rounded up to 16] with 31-bit byte offsets
-    const int64_t nsp = (int64_t)(g->ns + kTileRows - 1) / kTileRows * kTileRows;
-    if ((int64_t)pm->n_fft * nsp >= ((int64_t)1 << 28))
-        return fail(FH_E_UNSUPPORTED, "n_fft x spin-down rows = %lld reaches 2^28", (long long)pm->n_fft * nsp);
+    // the tiles address the shift records [row blocks][N] with 31-bit byte offsets
+    const int64_t nrb = (int64_t)(g->ns + kTileRows - 1) / kTileRows;
+    if ((int64_t)pm->n_fft * nrb >= ((int64_t)1 << 28))
+        return fail(FH_E_UNSUPPORTED, "n_fft x row blocks = %lld reaches 2^28", (long long)pm->n_fft * nrb);
     if (max_tile_bins(g->kf, row_step_bins(pm, g)) < 64)
         return fail(FH_E_UNSUPPORTED, "spin-down step of %.6g fine bins per row is too large for a tile",
                     row_step_bins(pm, g));
@@ -322,7 +337,9 @@ struct Timed {
 };
 
 struct ChunkBufs {
-    int64_t *gsh;  // [N][nsp] spin-down shifts of every row
+    int64_t *gwin;   // spin-down shift tables (ShiftLayout)
+    uint2 *rec;
+    uint32_t *step;
     uint32_t *Y;   // low words of the stripe edges (what the tiles read)
     int64_t *Y64;  // full stripe edges, only for the unfused window methods
     int2 *win, *wsort;
@@ -348,7 +365,8 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
                            int slots, int n_sky, bool weighted, hipStream_t st, ChunkBufs &b) {
     const int64_t N = pm->n_fft;
     fh_status s;
-    if ((s = ctx->cur->gsh.ensure((size_t)8 * N * p.nsp, st))) return s;
+    const ShiftLayout sl = shift_layout(N, p.nrb, p.nrbg);
+    if ((s = ctx->cur->sht.ensure(sl.total, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)4 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if (needs_full_edges(ctx, pm) &&
         (s = ctx->cur->Y64.ensure((size_t)8 * y_stride(pm->n_peaks, pm->n_fft) * slots, st)))
@@ -361,7 +379,9 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
     if ((s = ctx->cur->sky.ensure((size_t)24 * n_sky, st))) return s;
     if ((s = ctx->cur->qctr.ensure(4 * kXcds, st))) return s;
     if ((s = ctx->err.ensure(4, st))) return s;
-    b.gsh = (int64_t *)ctx->cur->gsh.ptr;
+    b.gwin = reinterpret_cast<int64_t *>((char *)ctx->cur->sht.ptr + sl.gwin);
+    b.rec = reinterpret_cast<uint2 *>((char *)ctx->cur->sht.ptr + sl.rec);
+    b.step = reinterpret_cast<uint32_t *>((char *)ctx->cur->sht.ptr + sl.step);
     b.Y = (uint32_t *)ctx->cur->Y.ptr;
     b.Y64 = (int64_t *)ctx->cur->Y64.ptr;
     b.win = (int2 *)ctx->cur->win.ptr;
@@ -390,8 +410,8 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.n_slots = slots;
     a.Y = b.Y;
     a.win = b.wsort;
-    a.gsh = b.gsh;
-    a.nsp = p.nsp;
+    a.rec = b.rec;
+    a.step = b.step;
     a.wq = weighted ? b.wq : nullptr;
     a.ws = weighted ? b.ws : nullptr;
     a.ws_stride = ws_stride;
@@ -425,7 +445,8 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                         int slots, const double *d_sky, const float *d_w, int w_stride,
                         const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
-    HIP_OK(launch_row_shifts(pm->n_fft, p.nsp, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot, b.gsh, st));
+    HIP_OK(launch_shift_tables(pm->n_fft, p.nrb, g->ns, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot,
+                               b.gwin, b.rec, b.step, b.err, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
     if (weighted)
@@ -435,7 +456,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     const double q = sm ? shift_reference_bins(ctx, pm, g) : 0.0;
     if (F > 0) {
         HIP_OK(launch_front(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots, g->kf,
-                            g->b0, b.gsh, p.nsp, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
+                            g->b0, b.gwin, b.Y, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, g->ns,
                             p.nrbg, p.nbb, p.W, F, pm->max_per_fft, b.win, sm, q, st));
         HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
         return FH_OK;
@@ -443,7 +464,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
     HIP_OK(launch_prep(pm->n_fft, pm->n_peaks, pm->d_offsets, pm->d_bins, pm->d_v, d_sky, slots,
                        g->kf, g->b0, b.Y64, d_w, w_stride, b.ws, w_stride == 0 ? 0 : 1, b.wq, b.Y, sm, q,
                        st));
-    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.gsh, p.nsp, g->ns, p.nrbg, p.nbb,
+    HIP_OK(launch_windows(pm->n_fft, pm->d_offsets, b.Y64, pm->n_peaks, b.gwin, p.nrbg, p.nbb,
                           p.W, g->kf, slots, b.win, ctx->window_method == 0 ? 0 : 1, st));
     HIP_OK(launch_sort_windows(pm->n_fft, p.nrbg, p.nbb, slots, b.win, b.wsort, st));
     return FH_OK;
@@ -745,6 +766,7 @@ fh_status fh_ctx_check(fh_ctx *ctx, void *stream) {
     int32_t flag = 0;
     HIP_OK(hipMemcpy(&flag, ctx->err.ptr, 4, hipMemcpyDeviceToHost));
     HIP_OK(hipMemset(ctx->err.ptr, 0, 4));
+    if (flag & 2) return fail(FH_E_DEVICE, "internal: a spin-down residual code left its 2-bit range");
     if (flag) return fail(FH_E_INVALID, "a weight vector held a value that is not finite or outside (0, 65536), or whose sum is too large");
     return FH_OK;
 }
@@ -1213,7 +1235,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->n_bin_blocks = p.nbb;
     out->workspace_bytes = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky +
-                           8 * (int64_t)pm->n_fft * p.nsp;
+                           (int64_t)shift_layout(pm->n_fft, p.nrb, p.nrbg).total;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
 }
@@ -1240,7 +1262,8 @@ namespace {
 // error flag and the queue counters are only read on paths this call does not
 // take (weights, the persistent schedule).
 struct StaticLayout {
-    size_t sky, err, qctr, gsh, y, y64, win, wsort, total;
+    size_t sky, err, qctr, sht, y, y64, win, wsort, total;
+    ShiftLayout shl;
 };
 
 StaticLayout static_layout(const fh_ctx *ctx, const fh_peakmap *pm, const Plan &p) {
@@ -1252,7 +1275,8 @@ StaticLayout static_layout(const fh_ctx *ctx, const fh_peakmap *pm, const Plan &
     L.sky = o;   o += al(24);
     L.err = o;   o += al(4);
     L.qctr = o;  o += al(4 * kXcds);
-    L.gsh = o;   o += al((size_t)8 * pm->n_fft * p.nsp);
+    L.shl = shift_layout(pm->n_fft, p.nrb, p.nrbg);
+    L.sht = o;   o += L.shl.total;
     L.y = o;     o += al(4 * ys);
     L.y64 = o;   if (needs_full_edges(ctx, pm)) o += al(8 * ys);
     L.win = o;   o += al(wins);
@@ -1286,7 +1310,9 @@ fh_status fh_hough_map_i32_static(fh_ctx *ctx, const fh_peakmap *pm, const doubl
     b.err = reinterpret_cast<int32_t *>(c + L.err);
     b.qctr = reinterpret_cast<int32_t *>(c + L.qctr);
     b.colmax = reinterpret_cast<unsigned long long *>(c + L.qctr);  // not written by the map path
-    b.gsh = reinterpret_cast<int64_t *>(c + L.gsh);
+    b.gwin = reinterpret_cast<int64_t *>(c + L.sht + L.shl.gwin);
+    b.rec = reinterpret_cast<uint2 *>(c + L.sht + L.shl.rec);
+    b.step = reinterpret_cast<uint32_t *>(c + L.sht + L.shl.step);
     b.Y = reinterpret_cast<uint32_t *>(c + L.y);
     b.Y64 = reinterpret_cast<int64_t *>(c + L.y64);
     b.win = reinterpret_cast<int2 *>(c + L.win);
@@ -1347,7 +1373,7 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
         (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)st, (uint64_t)(uintptr_t)b.Y,
         (uint64_t)(uintptr_t)b.win, (uint64_t)(uintptr_t)b.wsort, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.wq,
         (uint64_t)(uintptr_t)b.ws, (uint64_t)(uintptr_t)b.sky,
-        (uint64_t)(uintptr_t)b.gsh,
+        (uint64_t)(uintptr_t)b.gwin,
         (uint64_t)(uintptr_t)b.qctr, (uint64_t)(uintptr_t)b.Y64, (uint64_t)ctx->window_method,
         (uint64_t)ctx->doppler_mode, bits(ctx->doppler_fref)};
     fh_ctx::GraphEntry *ge = nullptr;
@@ -1470,7 +1496,8 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 // Byte layout of one search's workspace inside a block of the server's
 // arena: the same buffers ensure_workspace provides, 256-byte aligned.
 struct SearchLayout {
-    size_t gsh = 0, y = 0, y64 = 0, win = 0, wsort = 0, colmax = 0, wq = 0, ws = 0, sky = 0, qctr = 0, total = 0;
+    size_t sht = 0, y = 0, y64 = 0, win = 0, wsort = 0, colmax = 0, wq = 0, ws = 0, sky = 0, qctr = 0, total = 0;
+    ShiftLayout shl{};
 };
 
 SearchLayout search_layout(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int chunk,
@@ -1481,7 +1508,8 @@ SearchLayout search_layout(const fh_ctx *ctx, const fh_peakmap *pm, const fh_gri
     const size_t wins = (size_t)8 * c * p.nrbg * p.nbb * win_stride(pm->n_fft);
     SearchLayout L;
     size_t o = 0;
-    L.gsh = o;    o += al(8 * N * p.nsp);
+    L.shl = shift_layout((int64_t)N, p.nrb, p.nrbg);
+    L.sht = o;    o += L.shl.total;
     L.y = o;      o += al(4 * ys * c);
     L.y64 = o;    if (needs_full_edges(ctx, pm)) o += al(8 * ys * c);
     L.win = o;    o += al(wins);
@@ -1497,7 +1525,9 @@ SearchLayout search_layout(const fh_ctx *ctx, const fh_peakmap *pm, const fh_gri
 
 ChunkBufs carve(char *base, const SearchLayout &L, int32_t *err) {
     ChunkBufs b{};
-    b.gsh = reinterpret_cast<int64_t *>(base + L.gsh);
+    b.gwin = reinterpret_cast<int64_t *>(base + L.sht + L.shl.gwin);
+    b.rec = reinterpret_cast<uint2 *>(base + L.sht + L.shl.rec);
+    b.step = reinterpret_cast<uint32_t *>(base + L.sht + L.shl.step);
     b.Y = reinterpret_cast<uint32_t *>(base + L.y);
     b.Y64 = reinterpret_cast<int64_t *>(base + L.y64);
     b.win = reinterpret_cast<int2 *>(base + L.win);

@@ -52,10 +52,11 @@ def test_static_map_rejects_what_the_scratch_cannot_hold():
     from paper_1407_8333_amd import api, _lib
     print("case: static map over the scratch limit", flush=True)
     rng = synth.rng_for(31)
-    pm = synth.random_peakmap(2000, 1024.0, 100_000, 100_040, 0.05, rng)
+    pm = synth.random_peakmap(8000, 1024.0, 100_000, 100_040, 0.05, rng)
     t0 = 0.5 * (pm.t[0] + pm.t[-1])
-    # 2000 FFTs x 8192 rows: the shift table alone is 131 MB
-    grid = synth.Grid(kf=10, b0=10 * 100_000, nf=400, ns=8192, fdot0=-1e-14, dfdot=1e-18, t0=t0)
+    # 8000 FFTs over a band of 2^21 fine bins (841 tiles of 2496 bins): the
+    # two peak-window tables alone take 2 x 8 x 841 x 8064 bytes = 108 MB
+    grid = synth.Grid(kf=10, b0=10 * 100_000, nf=1 << 21, ns=16, fdot0=-1e-14, dfdot=1e-18, t0=t0)
     with api.Context(0) as ctx:
         dpm = ctx.upload(pm)
         out = torch.zeros((grid.ns, grid.nf), dtype=torch.int32, device="cuda")
