@@ -14,6 +14,7 @@ Contents
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -40,40 +41,60 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def _open(path):
+    """A loaded build of fh_oracle.c with its prototypes attached."""
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.fho_hough_map.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
+                                  f64, f64, f64, i32, i32, P]
+    lib.fho_hough_map.restype = ctypes.c_int
+    lib.fho_hough_map_mode.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
+                                       f64, f64, f64, i32, i32, i32, f64, P]
+    lib.fho_hough_map_mode.restype = ctypes.c_int
+    lib.fho_shift_center.argtypes = [i32, i32, f64, f64]
+    lib.fho_shift_center.restype = i64
+    lib.fho_candidates.argtypes = [P, i32, i32, i32, i32, i32, P, P]
+    lib.fho_candidates.restype = i32
+    lib.fho_row_shifts.argtypes = [i32, P, f64, f64, i32, f64, f64, i32, P]
+    lib.fho_row_shifts.restype = None
+    lib.fho_left_edges.argtypes = [i32, P, P, P, P, f64, P, i32, i64, f64, f64, f64,
+                                   i64, P, P, P]
+    lib.fho_left_edges.restype = ctypes.c_int
+    lib.fho_inv_doppler.argtypes = [i32, P, P, P]
+    lib.fho_inv_doppler.restype = None
+    lib.fho_center.argtypes = [i32, i32, f64]
+    lib.fho_center.restype = i64
+    lib.fho_set_threads.argtypes = [i32]
+    lib.fho_set_threads.restype = None
+    lib.fho_max_threads.argtypes = []
+    lib.fho_max_threads.restype = i32
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB):
                 build(force=False)
-            lib = ctypes.CDLL(_LIB)
-            P = ctypes.c_void_p
-            i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-            lib.fho_hough_map.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
-                                          f64, f64, f64, i32, i32, P]
-            lib.fho_hough_map.restype = ctypes.c_int
-            lib.fho_hough_map_mode.argtypes = [i32, P, P, P, P, f64, P, P, i32, i64, i32, i32,
-                                               f64, f64, f64, i32, i32, i32, f64, P]
-            lib.fho_hough_map_mode.restype = ctypes.c_int
-            lib.fho_shift_center.argtypes = [i32, i32, f64, f64]
-            lib.fho_shift_center.restype = i64
-            lib.fho_candidates.argtypes = [P, i32, i32, i32, i32, i32, P, P]
-            lib.fho_candidates.restype = i32
-            lib.fho_row_shifts.argtypes = [i32, P, f64, f64, i32, f64, f64, i32, P]
-            lib.fho_row_shifts.restype = None
-            lib.fho_left_edges.argtypes = [i32, P, P, P, P, f64, P, i32, i64, f64, f64, f64,
-                                           i64, P, P, P]
-            lib.fho_left_edges.restype = ctypes.c_int
-            lib.fho_inv_doppler.argtypes = [i32, P, P, P]
-            lib.fho_inv_doppler.restype = None
-            lib.fho_center.argtypes = [i32, i32, f64]
-            lib.fho_center.restype = i64
-            lib.fho_set_threads.argtypes = [i32]
-            lib.fho_set_threads.restype = None
-            lib.fho_max_threads.argtypes = []
-            lib.fho_max_threads.restype = i32
-            _lib = lib
+            _lib = _open(_LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def _library(path):
+    """Route every oracle call through another build of fh_oracle.c while the
+    context is open (the mutation test plants mistakes in copies of it)."""
+    global _lib
+    lib = _open(path)
+    with _lock:
+        saved, _lib = _lib, lib
+    try:
+        yield lib
+    finally:
+        with _lock:
+            _lib = saved
 
 
 def _ptr(a):
