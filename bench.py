@@ -183,15 +183,15 @@ def lds_probe():
     lib = ctypes.CDLL(PROBE_LIB)
     f = lib.fhp_lds_atomic
     d = ctypes.POINTER(ctypes.c_double)
-    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, d, d, d]
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, d, d, d, d]
     f.restype = ctypes.c_int
     out = {}
     for mode, name in [(0, "conflict_free"), (1, "random"), (2, "tile_pattern")]:
-        rate, lpc, ms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        rc = f(mode, 2000, 1024, ctypes.byref(rate), ctypes.byref(lpc), ctypes.byref(ms))
+        rate, lpc, ms, ghz = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = f(mode, 2000, 1024, ctypes.byref(rate), ctypes.byref(lpc), ctypes.byref(ms), ctypes.byref(ghz))
         if rc != 0:
             raise RuntimeError("LDS probe failed with HIP error %d" % rc)
-        out[name] = {"lanes_per_clk_per_cu": lpc.value, "tops": rate.value / 1e12}
+        out[name] = {"lanes_per_clk_per_cu": lpc.value, "tops": rate.value / 1e12, "clock_ghz": ghz.value}
     return out
 
 

@@ -13,8 +13,16 @@
 //      words (one column of 16 rows) at a column drawn from a hash, so the
 //      four groups of a wave collide on banks as the real tiles do
 //   3  one bank: every lane of a wave hits a different word of the same bank
+//   4  the tile pattern with one column per group for all 8 atomics of a
+//      round, so consecutive atomics of a lane hit the same word (as the
+//      updates of out-of-tile stripes do in the tiles' dump columns)
+//   5  the tile pattern with slanted stripes: lane j of a group hits column
+//      c + floor(j s / 8) with a slope s in [-40, 40] / 8 columns per row
+//      drawn per group, as a stripe crosses the 16 rows of a tile
 // Cycles come from the shader clock (clock64) around the loop, between two
-// workgroup barriers; the chip-wide rate from HIP events around the launch.
+// workgroup barriers, and the same interval on the constant 100 MHz clock
+// (wall_clock64) gives the shader clock's frequency under this load; the
+// chip-wide rate comes from HIP events around the launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,6 +44,7 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 
 __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t iters, uint32_t seed,
                                                          unsigned long long *__restrict__ cycles,
+                                                         unsigned long long *__restrict__ ticks,
                                                          uint32_t *__restrict__ sink) {
     __shared__ uint32_t lds[kWords];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -48,9 +57,16 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
             w = (uint32_t)((wave * kAddr + k) * 64 + lane);
         } else if (mode == 1) {
             w = hash32(seed ^ (uint32_t)(blockIdx.x * kThreads + tid) * 8u ^ (uint32_t)k * 0x9E3779B9u);
-        } else if (mode == 2) {
+        } else if (mode == 5) {
+            const uint32_t hh = hash32(seed ^ (uint32_t)(blockIdx.x * 64 + wave * 4 + (lane >> 4)) * 8u ^
+                                       (uint32_t)k * 0x9E3779B9u);
+            const int slope8 = (int)(hh >> 16) % 81 - 40;
+            const int col = (int)(hh % 1024u) + 512 + ((lane & 15) * slope8 >> 3);
+            w = (uint32_t)col * 16u + (uint32_t)(lane & 15);
+        } else if (mode == 2 || mode == 4) {
+            const uint32_t kk = mode == 2 ? (uint32_t)k : 0u;
             const uint32_t col = hash32(seed ^ (uint32_t)(blockIdx.x * 64 + wave * 4 + (lane >> 4)) * 8u ^
-                                        (uint32_t)k * 0x9E3779B9u) % 2048u;
+                                        kk * 0x9E3779B9u) % 2048u;
             w = col * 16u + (uint32_t)(lane & 15);
         } else {
             w = (uint32_t)lane * 32u + (uint32_t)(wave * kAddr + k) * 2048u;
@@ -58,6 +74,7 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
         a[k] = w & (kWords - 1);
     }
     __syncthreads();
+    const unsigned long long w0 = wall_clock64();
     const unsigned long long t0 = clock64();
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
@@ -65,7 +82,11 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
     }
     __syncthreads();
     const unsigned long long t1 = clock64();
-    if (tid == 0) cycles[blockIdx.x] = t1 - t0;
+    const unsigned long long w1 = wall_clock64();
+    if (tid == 0) {
+        cycles[blockIdx.x] = t1 - t0;
+        ticks[blockIdx.x] = w1 - w0;
+    }
     // keep the updates live: every word's count goes to memory
     for (int i = tid; i < kWords; i += kThreads) atomicAdd(sink + (i & 1023), lds[i]);
 }
@@ -74,31 +95,33 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
 
 extern "C" {
 
-// Run pattern `mode` (0-3) with `blocks` workgroups of 1024 threads, each
+// Run pattern `mode` (0-5) with `blocks` workgroups of 1024 threads, each
 // lane issuing 8 * iters atomics.  Outputs: chip-wide lane-ops per second
 // (HIP events around the launch), mean LDS atomic lanes per shader clock per
-// workgroup (clock64 around the loop), and the launch time in ms.  Returns 0,
-// or a HIP error code.
+// workgroup (clock64 around the loop), the launch time in ms, and the mean
+// shader clock in GHz over the loops (clock64 cycles per wall_clock64 tick
+// times 100 MHz).  Returns 0, or a HIP error code.
 int fhp_lds_atomic(int32_t mode, int32_t iters, int32_t blocks, double *lane_ops_per_s,
-                   double *lanes_per_clk, double *ms_out) {
-    if (mode < 0 || mode > 3 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
-    unsigned long long *cyc = nullptr;
+                   double *lanes_per_clk, double *ms_out, double *clock_ghz) {
+    if (mode < 0 || mode > 5 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
+    unsigned long long *cyc = nullptr, *tck = nullptr;
     uint32_t *sink = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&cyc, sizeof(unsigned long long) * (size_t)blocks);
+    if (e == hipSuccess) e = hipMalloc(&tck, sizeof(unsigned long long) * (size_t)blocks);
     if (e == hipSuccess) e = hipMalloc(&sink, 4 * 1024);
     if (e == hipSuccess) e = hipMemset(sink, 0, 4 * 1024);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     // one untimed launch first (code load, clocks ramping up)
     if (e == hipSuccess) {
-        k_lds_atomic<<<blocks, kThreads>>>(mode, iters, 12345u, cyc, sink);
+        k_lds_atomic<<<blocks, kThreads>>>(mode, iters, 12345u, cyc, tck, sink);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
     if (e == hipSuccess) {
-        k_lds_atomic<<<blocks, kThreads>>>(mode, iters, 67890u, cyc, sink);
+        k_lds_atomic<<<blocks, kThreads>>>(mode, iters, 67890u, cyc, tck, sink);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
@@ -107,20 +130,30 @@ int fhp_lds_atomic(int32_t mode, int32_t iters, int32_t blocks, double *lane_ops
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e == hipSuccess) {
         unsigned long long *h = new unsigned long long[blocks];
+        unsigned long long *w = new unsigned long long[blocks];
         e = hipMemcpy(h, cyc, sizeof(unsigned long long) * (size_t)blocks, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(w, tck, sizeof(unsigned long long) * (size_t)blocks, hipMemcpyDeviceToHost);
         if (e == hipSuccess) {
             const double lanes = (double)kThreads * kAddr * (double)iters;
-            double sum = 0.0;
-            for (int b = 0; b < blocks; ++b) sum += lanes / (double)(h[b] ? h[b] : 1);
+            double sum = 0.0, cyc_sum = 0.0, tick_sum = 0.0;
+            for (int b = 0; b < blocks; ++b) {
+                sum += lanes / (double)(h[b] ? h[b] : 1);
+                cyc_sum += (double)h[b];
+                tick_sum += (double)w[b];
+            }
             *lanes_per_clk = sum / blocks;
             *lane_ops_per_s = lanes * blocks / (ms * 1e-3);
             *ms_out = ms;
+            *clock_ghz = tick_sum > 0 ? cyc_sum / tick_sum * 0.1 : 0.0;
         }
         delete[] h;
+        delete[] w;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (cyc) (void)hipFree(cyc);
+    if (tck) (void)hipFree(tck);
     if (sink) (void)hipFree(sink);
     return (int)e;
 }
