@@ -145,6 +145,44 @@ def test_random_small_maps_edge_cases(ctx, seed):
     _assert_weighted_close(gotw, refw, wts)
 
 
+@pytest.mark.parametrize("ns,kf", [(1, 10), (2, 1), (5, 10), (6, 37), (7, 10), (17, 10), (21, 2), (22, 10), (38, 10)])
+def test_short_last_row_block(ctx, ns, kf):
+    """Grids whose last 16-row block is partly empty (1 to 15 rows of it
+    exist): maps, weighted maps, candidates of both schedules and column
+    maxima against the oracle."""
+    import torch
+    api = _api()
+    rng = synth.rng_for(700 + ns * 3 + kf)
+    print("case: short last row block ns=%d kf=%d" % (ns, kf), flush=True)
+    t_fft = 2048.0
+    pm = synth.random_peakmap(90, t_fft, 60_000, 60_400, 0.08, rng)
+    dfd = (1.0 / t_fft) / (90 * t_fft / 2)
+    grid = synth.Grid(kf=kf, b0=kf * 60_050, nf=kf * 300, ns=ns, fdot0=-(ns // 2) * dfd, dfdot=dfd,
+                      t0=float(pm.t[45]))
+    nhat = synth.sky_uniform(1, rng)[0]
+    ref = oracle.hough_map(pm, grid, nhat)
+    np.testing.assert_array_equal(_gpu_map(ctx, pm, grid, nhat), ref.astype(np.int32))
+    wts = rng.uniform(0.5, 1.5, pm.n_fft).astype(np.float32)
+    refw = oracle.hough_map(pm, grid, nhat, weights=wts.astype(np.float64))
+    _assert_weighted_close(_gpu_map(ctx, pm, grid, nhat, weights=wts), refw, wts)
+    sky = np.concatenate([nhat[None, :], synth.sky_uniform(2, rng)])
+    sel = synth.Selection(width=max(1, grid.nf // 4))
+    dpm = ctx.upload(pm)
+    raw_p = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=1)
+    raw_0 = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=0)
+    torch.cuda.synchronize()
+    assert torch.equal(raw_p, raw_0)
+    dec = api.decode_candidates(raw_p)
+    idx, val = oracle.candidates(ref, sel.width, sel.excl, sel.sep)
+    _check_candidates(dec, 0, idx, val, pm.n_fft, sel.theta)
+    val_c, row_c = api.fh_hough_colmax(ctx, dpm, sky[:1], grid)
+    torch.cuda.synchronize()
+    top = ref.max(axis=0)
+    np.testing.assert_array_equal(val_c.cpu().numpy()[0], top.astype(np.float32))
+    np.testing.assert_array_equal(row_c.cpu().numpy()[0], np.argmax(ref == top[None, :], axis=0))
+    dpm.release()
+
+
 def test_zero_peaks_gives_zero_map(ctx):
     t = synth.fft_times(5, 1024.0)
     pm = synth.Peakmap(1024.0, t, np.zeros((5, 3)), np.zeros(6, np.int64), np.zeros(0, np.int32))
