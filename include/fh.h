@@ -122,7 +122,9 @@ typedef enum {
 
 typedef struct {
     int32_t schedule;    /* fh_schedule                                            */
-    int32_t tile_bins;   /* fine bins per LDS tile; 0 = library choice (autotuned) */
+    int32_t tile_bins;   /* fine bins per LDS tile; 0 = library choice (autotuned).
+                            A requested width is rounded up to a multiple of 64
+                            and capped at what one 16-row tile holds in LDS */
     int32_t sky_chunk;   /* sky directions per workspace chunk; 0 = library choice */
     int32_t use_graph;   /* 1: capture the whole search in a hipGraph on first use
                             and replay it while every pointer and shape argument
@@ -131,9 +133,13 @@ typedef struct {
 
 /* Tile / workspace plan reported by fh_plan_query. */
 typedef struct {
-    int32_t tile_rows;       /* spin-down rows per LDS tile                */
+    int32_t tile_rows;       /* spin-down rows per LDS tile (16)           */
     int32_t tile_bins;       /* fine bins per LDS tile                     */
-    int32_t n_row_blocks;
+    int32_t n_row_blocks;    /* 16-row blocks run as tiles: ceil(ns / 16),
+                                less one when the grid's last block holds
+                                1-3 rows and the tile width leaves room for
+                                them, in which case the tiles of the block
+                                before it also accumulate those rows      */
     int32_t n_bin_blocks;
     int64_t workspace_bytes; /* library workspace for one sky direction   */
     int64_t cell_updates;    /* peaks x rows, per sky direction           */

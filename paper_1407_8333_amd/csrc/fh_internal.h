@@ -32,6 +32,12 @@ constexpr int kLdsBytes = 163840;
 constexpr int kLdsReserve = 256;
 // dump columns after a tile's W + K_f - 1 columns (one per lane group)
 constexpr int kDumpCols = 4;
+// A last row block of at most kTailRows grid rows is not run as tiles of its
+// own: the tiles of the row block before it also accumulate those rows, one
+// atomic per peak and row, in LDS rows after their 16.
+constexpr int kTailRows = 3;
+// dump words after a tail row's W + K_f - 1 columns (one per lane of a wave)
+constexpr int kTailDump = 64;
 // Number of XCDs of an MI355X; workgroup w is dispatched to XCD w % 8.
 constexpr int kXcds = 8;
 // Padding entries after each FFT's stripe edges (never inside a window).
@@ -55,7 +61,8 @@ struct TileArgs {
     int32_t n_fft;
     int64_t n_peaks;
     int32_t kf, nf, ns, W;        // W: fine bins per tile
-    int32_t nrb, nbb, nrbg;       // row blocks, bin blocks, row-block groups
+    int32_t nrb, nbb, nrbg;       // row blocks run by the tiles, bin blocks, row-block groups
+    int32_t tail;                 // grid rows past the last run row block (0..kTailRows), done by its tiles
     int32_t n_slots;              // sky directions in this chunk
     const uint32_t *Y;            // [slot][P] low words of the stripe edges (2^-16 fine bins)
     const int2 *win;              // [slot][nrbg][nbb][win_stride(N)] sorted windows
@@ -80,7 +87,10 @@ hipError_t launch_set_f64x3(double *p, double x, double y, double z, hipStream_t
 // spin-down shift tables of G_is = rint(((fdot0 + s dfdot) (t_i - t0)) (K_f T_FFT) 2^16):
 // gwin [N][nrbg][2] (first and last grid row of each row group), rec [nrb][N],
 // step [N][16] (see k_shift_tables); err bit 2 if a residual code overflows
-hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *t, double t0, double t_fft,
+// (nrb row blocks of records; windows for the row groups of the first
+// nrb_run blocks, the last group reaching the grid's last row)
+hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t nrb_run, int32_t ns, const double *t, double t0,
+                               double t_fft,
                                int32_t kf, double fdot0, double dfdot, int64_t *gwin, uint2 *rec, uint32_t *step,
                                int32_t *err, hipStream_t st);
 hipError_t launch_weight_stats(int32_t n_fft, int32_t n_vec, const float *w, int32_t w_stride,
@@ -162,12 +172,13 @@ hipError_t launch_robust(const int32_t *x, int32_t n, int32_t x_max, int32_t *hi
 hipError_t launch_colmax_decode(const unsigned long long *colmax, int32_t nf, int32_t n_slots, const WeightStats *ws,
                                 int32_t ws_stride, float *value, int32_t *row, hipStream_t st);
 hipError_t launch_colmax_values(const unsigned long long *colmax, int32_t nf, int32_t *out, hipStream_t st);
-int tile_lds_bytes(int W, int kf);
+// LDS bytes of a tile of 16 + tail rows
+int tile_lds_bytes(int W, int kf, int tail);
 // Raise the dynamic-LDS limit of the tile kernels (once per device).
 hipError_t init_kernel_attributes();
-// widest tile (multiple of 64) that the LDS holds and that keeps 32-bit
-// tile-relative stripe edges exact when a row's spin-down step is at most
-// step_bins fine bins; 0 when no tile does
-int max_tile_bins(int kf, double step_bins);
+// widest tile (multiple of 64) of `rows` LDS rows that the LDS holds and
+// that keeps 32-bit tile-relative stripe edges exact when a row's spin-down
+// step is at most step_bins fine bins; 0 when no tile does
+int max_tile_bins(int kf, double step_bins, int rows);
 
 }  // namespace fh

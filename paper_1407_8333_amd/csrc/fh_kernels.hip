@@ -46,8 +46,9 @@ constexpr int64_t kYSentinel = (int64_t)1 << 61;
 // Tile-relative edges are 32-bit: with kFrac = 16 fractional bits a column is
 // the upper half-word, inside +-2^15.  A peak of a window starts within 64
 // rows' worth of spin-down steps of the tile (the window covers a group of
-// 64 rows, the last row block may reach 16 rows past the grid), so
-// max_tile_bins bounds W + K_f + 80 (step + 1) + 64 below 2^15.  kFarEdge
+// 64 rows, the last group up to kTailRows more; the last row block may reach
+// 16 rows past the grid), so max_tile_bins bounds W + K_f + 80 (step + 1) +
+// 64 below 2^15.  kFarEdge
 // (16384 bins) then stays in range and beyond the dump column for every row.
 constexpr uint32_t kFarEdge = 16384u << kFrac;
 
@@ -101,11 +102,14 @@ __device__ __forceinline__ int64_t row_shift(double tau, double S, double fdot0,
 //                 group g), for the peak windows                   [N][nrbg][2]
 // A code outside {-1 .. 2} (impossible by the bound above) sets bit 2 of the
 // error flag.
-__global__ void k_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *__restrict__ t, double t0,
+__global__ void k_shift_tables(int32_t n_fft, int32_t nrb, int32_t nrb_run, int32_t ns,
+                               const double *__restrict__ t, double t0,
                                double S, double fdot0, double dfdot, int64_t *__restrict__ gwin,
                                uint2 *__restrict__ rec, uint32_t *__restrict__ step,
                                int32_t *__restrict__ err) {
-    const int32_t nrbg = (nrb + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
+    // row groups of the row blocks the tiles run; the last one reaches the
+    // grid's last row (the rows of a folded last block included)
+    const int32_t nrbg = (nrb_run + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
     const int64_t n = (int64_t)n_fft * nrb;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t rb = (int32_t)(x / n_fft);
@@ -127,9 +131,9 @@ __global__ void k_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const dou
         }
         rec[(int64_t)rb * n_fft + i] = make_uint2((uint32_t)(uint64_t)g0, codes);
         if (bad) atomicOr(err, 2);
-        if (rb % kRowBlocksPerGroup == 0) {
+        if (rb < nrb_run && rb % kRowBlocksPerGroup == 0) {
             const int32_t g = rb / kRowBlocksPerGroup;
-            const int32_t s_hi = min(s0 + kRowBlocksPerGroup * kTileRows - 1, ns - 1);
+            const int32_t s_hi = g == nrbg - 1 ? ns - 1 : s0 + kRowBlocksPerGroup * kTileRows - 1;
             gwin[((int64_t)i * nrbg + g) * 2] = g0;
             gwin[((int64_t)i * nrbg + g) * 2 + 1] = row_shift(tau, S, fdot0, dfdot, s_hi);
         }
@@ -736,6 +740,33 @@ __device__ __forceinline__ void stripe_chunk(uint32_t m, uint32_t v, uint32_t t,
     if (m & 0x8000u) stripe_run<15, 16>(v, t, dump, lane_off, val, lds);
 }
 
+// Tail rows (rows 16 .. 16 + A.tail - 1 of the tiles of the last run row
+// block): every pattern lane adds its own peak's stripe start in each tail
+// row, one atomic per peak and row, in the row-major tail region `lt` (row
+// stride `stride` words).  Lane r of a group holds the group's tail row term
+// of row 16 + r, broadcast to the group by DPP row_newbcast:r fused into the
+// add; lanes outside the chunk's pattern (which may repeat a pattern lane's
+// peak) and starts outside the tile go to the lane's own dump word, so that
+// no two lanes of an atomic update one word.
+template <int R>
+__device__ __forceinline__ void tail_row(uint32_t v, uint32_t tt, uint32_t dump, uint32_t val,
+                                         uint32_t *__restrict__ lt) {
+    const uint32_t b = __builtin_amdgcn_update_dpp(0u, tt, 0x150 + R, 0xF, 0xF, true);
+    const uint16_t col = (uint16_t)((v + b) >> kFrac);
+    const uint32_t cu = col < (uint16_t)dump ? col : (uint16_t)dump;
+    atomicAdd(lt + cu, val);
+}
+
+__device__ __forceinline__ void tail_steps(int rows, uint32_t m, uint32_t j, uint32_t v, uint32_t tt,
+                                           uint32_t dump, uint32_t stride, uint32_t val,
+                                           uint32_t *__restrict__ lt) {
+    static_assert(kTailRows == 3, "tail_steps unrolls kTailRows rows");
+    const uint32_t vv = (m >> j) & 1u ? v : kFarEdge;
+    tail_row<0>(vv, tt, dump, val, lt);
+    if (rows > 1) tail_row<1>(vv, tt, dump, val, lt + stride);
+    if (rows > 2) tail_row<2>(vv, tt, dump, val, lt + 2 * stride);
+}
+
 // One block: four consecutive FFTs of a sorted run, entry 4 b + g in lane
 // group g.  Lane (g, j) holds its group's window, row term and weight, and
 // the stripe edges of its peaks in up to two chunks of 16.
@@ -744,6 +775,7 @@ struct Quad {
     int lo, pk;          // window start; FFT place in the run << 16 | peak count
     uint32_t gb;         // G_{i,s0} of the group's FFT i (mod 2^32)
     uint32_t t, wq;      // row term G_{i,s0} - G_{i,s0+j} (mod 2^32); fixed-point weight
+    uint32_t tt;         // tail row term G_{i,s0} - G_{i,s0+16+j} (mod 2^32), tiles with tail rows
     int cnt;             // peaks in the window (0 past the tile's blocks)
     int32_t q1, q2;      // chunk positions of the lane's peaks
     uint32_t y0, y1;     // low words of their stripe edges
@@ -790,9 +822,11 @@ __device__ int steal_tile(const TileArgs &A, int home) {
     return -1;
 }
 
-// LDS words of a tile: W + K_f - 1 columns plus the dump columns, 16 rows.
+// LDS words of a tile: W + K_f - 1 columns plus the dump columns, 16 rows
+// (column-major), then A.tail rows of W + K_f - 1 + kTailDump words
+// (row-major).
 __device__ __forceinline__ int tile_words(const TileArgs &A) {
-    return kTileRows * (A.W + A.kf - 1 + kDumpCols);
+    return kTileRows * (A.W + A.kf - 1 + kDumpCols) + A.tail * (A.W + A.kf - 1 + kTailDump);
 }
 
 __device__ __forceinline__ void tile_zero(const TileArgs &A, uint32_t *__restrict__ lds) {
@@ -1020,6 +1054,46 @@ __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb,
     }
 }
 
+// Output of the tail rows of a tile (rows (rb + 1) 16 + r, r < A.tail): their
+// window sums, one thread per column summing K_f start counts per row, as a
+// map and/or raised into the column maxima; then, after a barrier, the tail
+// region is cleared for the next tile.  Reads only the tail region, so it
+// may follow either output phase of the 16 rows without a barrier between.
+template <bool WEIGHTED, bool MAP, bool COLMAX>
+__device__ __forceinline__ void tail_output(const TileArgs &A, int slot, int rb, int jb,
+                                            uint32_t *__restrict__ lt) {
+    const int W = A.W, kf = A.kf;
+    const int stride = W + kf - 1 + kTailDump;
+    const int s_t = (rb + 1) * kTileRows;  // first tail row
+    const int64_t bbase = (int64_t)jb * W;
+    const int xend = (int)min((int64_t)W, (int64_t)A.nf - bbase);
+    unsigned long long *__restrict__ cm = A.colmax + (int64_t)slot * A.nf + bbase;
+    float scale = 1.0f;
+    if (WEIGHTED) scale = ldexpf(1.0f, -A.ws[(int64_t)slot * A.ws_stride].frac_bits);
+    for (int x = threadIdx.x; x < xend; x += blockDim.x) {
+        uint32_t top = 0;
+        int brow = 0;
+        for (int r = 0; r < A.tail; ++r) {
+            const uint32_t *P = lt + r * stride + x;
+            uint32_t acc = 0;
+            for (int c = 0; c < kf; ++c) acc += P[c];
+            if (MAP) {
+                const int64_t idx = (int64_t)(s_t + r) * A.nf + bbase + x;
+                if (WEIGHTED) A.map_f32[idx] = (float)acc * scale;
+                else A.map_i32[idx] = (int32_t)acc;
+            }
+            if (acc > top) {  // the smallest row holding the maximum
+                top = acc;
+                brow = r;
+            }
+        }
+        if (COLMAX) atomicMax(cm + x, ((unsigned long long)top << 32) | (0xFFFFFFFFull - (unsigned)(s_t + brow)));
+    }
+    lds_barrier();
+    const int nwords = A.tail * stride;
+    for (int x = threadIdx.x; x < nwords; x += blockDim.x) lt[x] = 0;
+}
+
 // The tiles of one workgroup.  The waves take the tile's blocks (four FFTs
 // of a sorted run, one per lane group; windows past the last FFT are empty)
 // from a counter in LDS, so that each wave takes as many as it can process.
@@ -1030,7 +1104,7 @@ __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb,
 // path so that the wait counts stay exact.  PERSISTENT: tiles come from the
 // XCD queues until all are exhausted; otherwise the workgroup runs tile
 // tile_base + blockIdx.x only.
-template <bool WEIGHTED, bool MAP, bool COLMAX, bool PERSISTENT>
+template <bool WEIGHTED, bool MAP, bool COLMAX, bool PERSISTENT, bool TAIL>
 __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restrict__ lds, int *s_next,
                                           int *s_cnt) {
     const int tid = threadIdx.x;
@@ -1053,6 +1127,11 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     const int home = blockIdx.x % kXcds;
     const __amdgpu_buffer_rsrc_t r_rec = buf(A.rec), r_step = buf(A.step);
     const uint32_t lane_code = 2u * (uint32_t)j;  // bit offset of this row's residual code
+    // tail rows after the 16-row tile (row-major, rows of wc + kTailDump
+    // words; every lane of a wave has its own dump word in each row)
+    const uint32_t t_stride = (uint32_t)(wc + kTailDump);
+    const uint32_t t_dump = (uint32_t)(wc + lane);
+    uint32_t *__restrict__ const ltail = lds + kTileRows * (wc + kDumpCols);
 
     // per-tile buffers: window row, stripe edges and weights of the slot
     struct Bufs {
@@ -1106,6 +1185,17 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         Q.gb = (uint32_t)r[0];
         const uint32_t code = __builtin_amdgcn_ubfe((uint32_t)r[1], lane_code, 2u);
         Q.t = (1u - ld_u32(r_step, (fc * kTileRows + (uint32_t)j) * 4u)) - code;
+        // tiles with tail rows: G_{i,s0} - G_{i,s0+16+j} from the next row
+        // block's record, whose rows share this block's linear steps (other
+        // row blocks read their own record and leave the term unused; no
+        // branch, so that nothing here waits for the loads)
+        Q.tt = 0u;
+        if (TAIL) {
+            const uint32_t rb2 = B.rb + (B.rb == (uint32_t)(A.nrb - 1) ? 1u : 0u);
+            const auto r2 = __builtin_amdgcn_raw_buffer_load_b64(r_rec, (rb2 * (uint32_t)A.n_fft + fc) * 8u, 0, 0);
+            const uint32_t code2 = __builtin_amdgcn_ubfe((uint32_t)r2[1], lane_code, 2u);
+            Q.tt = Q.t + code - code2 + (Q.gb - (uint32_t)r2[0]);
+        }
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
         Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
@@ -1142,15 +1232,18 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         int slot, rb, jb;
         decode_tile(A, t, slot, rb, jb);
         const uint32_t c0q = (uint32_t)(jb * W - (kf - 1)) << kFrac;
+        const bool tailed = TAIL && rb == A.nrb - 1;  // this tile also does the tail rows
         auto consume = [&](const Quad &Q) {
             const uint32_t base = c0q + Q.gb;
             uint32_t val = Q.wq;
             asm volatile("" : "+v"(val));
             const uint32_t v0 = Q.q1 < Q.cnt ? Q.y0 - base : kFarEdge;
             stripe_chunk(Q.m1, v0, Q.t, dump, lane_off, val, lds);
+            if (tailed) tail_steps(A.tail, Q.m1, lane_off, v0, Q.tt, t_dump, t_stride, val, ltail);
             if (Q.cmax > 16) {
                 const uint32_t v1 = Q.q2 < Q.cnt ? Q.y1 - base : kFarEdge;
                 stripe_chunk(Q.m2, v1, Q.t, dump, lane_off, val, lds);
+                if (tailed) tail_steps(A.tail, Q.m2, lane_off, v1, Q.tt, t_dump, t_stride, val, ltail);
             }
             // windows longer than 32 peaks: further chunks, loaded here
             for (int off = 32; off < Q.cmax; off += 16) {
@@ -1159,6 +1252,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
                 uint32_t v = kFarEdge;
                 if (q < Q.cnt) v = ld_u32(cur.y, (uint32_t)(Q.lo + q) * 4u) - base;
                 stripe_chunk(m, v, Q.t, dump, lane_off, val, lds);
+                if (tailed) tail_steps(A.tail, m, lane_off, v, Q.tt, t_dump, t_stride, val, ltail);
             }
         };
         // Ring of three blocks: a block's window is loaded two blocks ahead,
@@ -1211,6 +1305,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         } else {
             tile_output<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, lds);
         }
+        if (TAIL && tailed) tail_output<WEIGHTED, MAP, COLMAX>(A, slot, rb, jb, ltail);
         if (tn < 0) break;
         if (!fused) stage_y(qa, nxt);
         lds_barrier();
@@ -1223,23 +1318,23 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
     }
 }
 
-template <bool WEIGHTED, bool MAP, bool COLMAX>
+template <bool WEIGHTED, bool MAP, bool COLMAX, bool TAIL>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_plain(TileArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ int s_cnt[2];
-    run_tiles<WEIGHTED, MAP, COLMAX, false>(A, lds, nullptr, s_cnt);
+    run_tiles<WEIGHTED, MAP, COLMAX, false, TAIL>(A, lds, nullptr, s_cnt);
 }
 
 // One workgroup per CU.  The next tile of the home queue is claimed when a
 // tile starts (its counter update overlaps the tile's work) and used when it
 // ends; an exhausted home queue sends the workgroup to the others.  Every
 // workgroup leaves the loop once all queues are exhausted.
-template <bool WEIGHTED, bool MAP, bool COLMAX>
+template <bool WEIGHTED, bool MAP, bool COLMAX, bool TAIL>
 __global__ void __launch_bounds__(kTileThreads) k_tiles_persistent(TileArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ int s_next[2];
     __shared__ int s_cnt[2];
-    run_tiles<WEIGHTED, MAP, COLMAX, true>(A, lds, s_next, s_cnt);
+    run_tiles<WEIGHTED, MAP, COLMAX, true, TAIL>(A, lds, s_next, s_cnt);
 }
 
 // ----------------------------------------------------------------------------
@@ -1445,11 +1540,14 @@ inline unsigned grid_for(int64_t n, int block) {
 
 }  // namespace
 
-int tile_lds_bytes(int W, int kf) { return kTileRows * (W + kf - 1 + kDumpCols) * 4; }
+int tile_lds_bytes(int W, int kf, int tail) {
+    return (kTileRows * (W + kf - 1 + kDumpCols) + tail * (W + kf - 1 + kTailDump)) * 4;
+}
 
-int max_tile_bins(int kf, double step_bins) {
-    const int words = (kLdsBytes - kLdsReserve) / 4 / kTileRows;  // columns incl. dumps
-    int w = words - kf + 1 - kDumpCols;                           // W + kf - 1 + dumps <= words
+int max_tile_bins(int kf, double step_bins, int rows) {
+    // rows past 16 are tail rows, with kTailDump dump words each
+    const int words = (kLdsBytes - kLdsReserve) / 4 - kDumpCols * kTileRows - kTailDump * (rows - kTileRows);
+    int w = words / rows - kf + 1;  // rows (W + kf - 1) + dump words <= words
     // supported row steps: below 128 fine bins
     if (step_bins * kQd + 1.0 >= 8388608.0) return 0;
     // 32-bit tile-relative edges (see kFarEdge)
@@ -1476,13 +1574,16 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t ns, const double *t, double t0, double t_fft,
+hipError_t launch_shift_tables(int32_t n_fft, int32_t nrb, int32_t nrb_run, int32_t ns, const double *t, double t0,
+                               double t_fft,
                                int32_t kf, double fdot0, double dfdot, int64_t *gwin, uint2 *rec, uint32_t *step,
                                int32_t *err, hipStream_t st) {
     const int64_t n = (int64_t)n_fft * nrb;
     if (n <= 0) return hipSuccess;
+    if (nrb_run < 1 || nrb_run > nrb) return hipErrorInvalidValue;
     const double S = ((double)kf * t_fft) * kQd;
-    k_shift_tables<<<grid_for(n, 256), 256, 0, st>>>(n_fft, nrb, ns, t, t0, S, fdot0, dfdot, gwin, rec, step, err);
+    k_shift_tables<<<grid_for(n, 256), 256, 0, st>>>(n_fft, nrb, nrb_run, ns, t, t0, S, fdot0, dfdot, gwin, rec,
+                                                     step, err);
     return hipGetLastError();
 }
 
@@ -1550,24 +1651,41 @@ hipError_t launch_windows(int32_t n_fft, const int64_t *offsets, const int64_t *
     return hipGetLastError();
 }
 
-template <bool Wt, bool M, bool C>
-static hipError_t set_tile_attrs() {
+template <bool Wt, bool M, bool C, bool T>
+static hipError_t set_tile_attrs_t() {
     const int lds = kLdsBytes - kLdsReserve;
-    hipError_t e = hipFuncSetAttribute((const void *)k_tiles_persistent<Wt, M, C>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_tiles_persistent<Wt, M, C, T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_tiles_plain<Wt, M, C>,
+    return hipFuncSetAttribute((const void *)k_tiles_plain<Wt, M, C, T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 template <bool Wt, bool M, bool C>
+static hipError_t set_tile_attrs() {
+    const hipError_t e = set_tile_attrs_t<Wt, M, C, false>();
+    return e != hipSuccess ? e : set_tile_attrs_t<Wt, M, C, true>();
+}
+
+// Tiles with tail rows run the TAIL form of the kernels; without, the plain
+// form has no trace of them.
+template <bool Wt, bool M, bool C>
 static hipError_t launch_tiles_t(const TileArgs &a, bool persistent, int32_t n_tiles,
                                  int32_t grid_blocks, hipStream_t st) {
-    const int lds = tile_lds_bytes(a.W, a.kf);
-    if (persistent)
-        k_tiles_persistent<Wt, M, C><<<grid_blocks, kTileThreads, lds, st>>>(a);
-    else
-        k_tiles_plain<Wt, M, C><<<n_tiles, kTileThreads, lds, st>>>(a);
+    if (a.tail < 0 || a.tail > kTailRows) return hipErrorInvalidValue;
+    const int lds = tile_lds_bytes(a.W, a.kf, a.tail);
+    if (lds > kLdsBytes - kLdsReserve) return hipErrorInvalidValue;
+    if (a.tail > 0) {
+        if (persistent)
+            k_tiles_persistent<Wt, M, C, true><<<grid_blocks, kTileThreads, lds, st>>>(a);
+        else
+            k_tiles_plain<Wt, M, C, true><<<n_tiles, kTileThreads, lds, st>>>(a);
+    } else {
+        if (persistent)
+            k_tiles_persistent<Wt, M, C, false><<<grid_blocks, kTileThreads, lds, st>>>(a);
+        else
+            k_tiles_plain<Wt, M, C, false><<<n_tiles, kTileThreads, lds, st>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -197,8 +197,12 @@ struct fh_ctx {
 
 namespace {
 
+// nrb: row blocks the tiles run (the last one also takes `tail` rows past it
+// when the grid's last 16-row block holds at most kTailRows rows); nrb_tab:
+// every 16-row block of the grid (the shift records cover them all).
 struct Plan {
     int W, nrb, nbb, nrbg;
+    int nrb_tab, tail;
     int64_t tiles_per_sky;
 };
 
@@ -219,10 +223,22 @@ ShiftLayout shift_layout(int64_t n_fft, int nrb, int nrbg) {
     return L;
 }
 
+// Rows of the grid's last 16-row block when the tiles of the block before
+// it take them (at most kTailRows, and a block before it exists), else 0.
+int tail_rows(const fh_grid &g) {
+    const int nrb = (g.ns + kTileRows - 1) / kTileRows;
+    const int r = g.ns - (nrb - 1) * kTileRows;
+    return nrb >= 2 && r <= kTailRows ? r : 0;
+}
+
 Plan make_plan(const fh_grid &g, int W) {
     Plan p;
     p.W = W;
-    p.nrb = (g.ns + kTileRows - 1) / kTileRows;
+    p.nrb_tab = (g.ns + kTileRows - 1) / kTileRows;
+    // the tail rows are folded only where the wider tile still fits the LDS
+    p.tail = tail_rows(g);
+    if (p.tail && tile_lds_bytes(W, g.kf, p.tail) > kLdsBytes - kLdsReserve) p.tail = 0;
+    p.nrb = p.nrb_tab - (p.tail ? 1 : 0);
     p.nbb = (g.nf + W - 1) / W;
     p.nrbg = (p.nrb + kRowBlocksPerGroup - 1) / kRowBlocksPerGroup;
     p.tiles_per_sky = (int64_t)p.nrb * p.nbb;
@@ -243,8 +259,12 @@ double row_step_bins(const fh_peakmap *pm, const fh_grid *g) {
     return std::fabs(g->dfdot) * tau * ((double)g->kf * pm->t_fft) + 1e-6;
 }
 
+// Widest tile for the grid: its LDS also holds the tail rows when the grid
+// has some, unless that leaves no tile of 64 bins (then they run as a row
+// block of their own).
 int tile_bins_limit(const fh_peakmap *pm, const fh_grid *g) {
-    return max_tile_bins(g->kf, row_step_bins(pm, g));
+    const int w = max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows + tail_rows(*g));
+    return w >= 64 ? w : max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows);
 }
 
 fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
@@ -269,7 +289,7 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     const int64_t nrb = (int64_t)(g->ns + kTileRows - 1) / kTileRows;
     if ((int64_t)pm->n_fft * nrb >= ((int64_t)1 << 28))
         return fail(FH_E_UNSUPPORTED, "n_fft x row blocks = %lld reaches 2^28", (long long)pm->n_fft * nrb);
-    if (max_tile_bins(g->kf, row_step_bins(pm, g)) < 64)
+    if (max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows) < 64)
         return fail(FH_E_UNSUPPORTED, "spin-down step of %.6g fine bins per row is too large for a tile",
                     row_step_bins(pm, g));
     return FH_OK;
@@ -288,10 +308,15 @@ std::tuple<int, int, int, int, int> tune_key(const fh_peakmap *pm, const fh_grid
     return std::make_tuple(pm->n_fft, g->nf, g->ns, g->kf, weighted ? 1 : 0);
 }
 
+// Tile width: the requested one (multiple of 64, at most what a 16-row tile
+// holds; a width too wide for the tail rows runs them as a row block of
+// their own), else the autotuned one, else the widest that also holds the
+// tail rows.
 int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested,
                      bool weighted = false) {
     const int wmax = tile_bins_limit(pm, g);
-    if (requested > 0) return std::min(((requested + 63) / 64) * 64, wmax);
+    if (requested > 0)
+        return std::min(((requested + 63) / 64) * 64, max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows));
     auto it = ctx->tuned.find(tune_key(pm, g, weighted));
     if (it != ctx->tuned.end()) return it->second;
     // a tile never needs to be wider than the map
@@ -365,7 +390,7 @@ fh_status ensure_workspace(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, 
                            int slots, int n_sky, bool weighted, hipStream_t st, ChunkBufs &b) {
     const int64_t N = pm->n_fft;
     fh_status s;
-    const ShiftLayout sl = shift_layout(N, p.nrb, p.nrbg);
+    const ShiftLayout sl = shift_layout(N, p.nrb_tab, p.nrbg);
     if ((s = ctx->cur->sht.ensure(sl.total, st))) return s;
     if ((s = ctx->cur->Y.ensure((size_t)4 * y_stride(pm->n_peaks, pm->n_fft) * slots, st))) return s;
     if (needs_full_edges(ctx, pm) &&
@@ -405,6 +430,7 @@ TileArgs tile_args(const fh_peakmap *pm, const fh_grid *g, const Plan &p, int sl
     a.ns = g->ns;
     a.W = p.W;
     a.nrb = p.nrb;
+    a.tail = p.tail;
     a.nbb = p.nbb;
     a.nrbg = p.nrbg;
     a.n_slots = slots;
@@ -445,7 +471,7 @@ fh_status enqueue_front(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, con
                         int slots, const double *d_sky, const float *d_w, int w_stride,
                         const ChunkBufs &b, hipStream_t st) {
     Timed timed(ctx, st, kSpanFront);
-    HIP_OK(launch_shift_tables(pm->n_fft, p.nrb, g->ns, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot,
+    HIP_OK(launch_shift_tables(pm->n_fft, p.nrb_tab, p.nrb, g->ns, pm->d_t, g->t0, pm->t_fft, g->kf, g->fdot0, g->dfdot,
                                b.gwin, b.rec, b.step, b.err, st));
     const bool weighted = d_w != nullptr;
     const int n_vec = weighted ? (w_stride == 0 ? 1 : slots) : 0;
@@ -565,17 +591,22 @@ fh_status run_search(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const 
 
 // Tile-width autotuner: times the persistent search of a sample of the
 // directions for each candidate width (multiples of 64 up to what the LDS
-// holds) and keeps the fastest per problem shape and weighting.
+// holds) and keeps the fastest per problem shape and weighting.  With tail
+// rows, the widest 16-row tile (too wide to hold them, so they run as a row
+// block of their own) is a candidate too.
 fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sky,
                    const double *sky, const float *d_w, int w_stride, hipStream_t st) {
     const bool weighted = d_w != nullptr;
     const int wmax = tile_bins_limit(pm, g);
-    const int wcap = std::min(wmax, std::max(64, ((g->nf + 63) / 64) * 64));
+    const int wmap = std::max(64, ((g->nf + 63) / 64) * 64);  // a tile never needs to be wider than the map
+    const int wcap = std::min(wmax, wmap);
     std::vector<int> cands;
     for (int w : {512, 832, 1280, 1792, 2176})
         if (w < wcap) cands.push_back(w);
     cands.push_back(wcap);
-    const int sample = std::min(n_sky, 16);
+    const int w16 = std::min(max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows), wmap);
+    if (w16 > wcap) cands.push_back(w16);
+    const int sample = std::min(n_sky, 64);
     const bool was = ctx->profiling;
     ctx->profiling = false;
     hipEvent_t e0, e1;
@@ -1235,7 +1266,7 @@ fh_status fh_plan_query(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int
     out->n_bin_blocks = p.nbb;
     out->workspace_bytes = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) +
                            8 * (int64_t)g->nf + 4 * (int64_t)pm->n_fft + 4 * p.tiles_per_sky +
-                           (int64_t)shift_layout(pm->n_fft, p.nrb, p.nrbg).total;
+                           (int64_t)shift_layout(pm->n_fft, p.nrb_tab, p.nrbg).total;
     out->cell_updates = pm->n_peaks * (int64_t)g->ns;
     return FH_OK;
 }
@@ -1275,7 +1306,7 @@ StaticLayout static_layout(const fh_ctx *ctx, const fh_peakmap *pm, const Plan &
     L.sky = o;   o += al(24);
     L.err = o;   o += al(4);
     L.qctr = o;  o += al(4 * kXcds);
-    L.shl = shift_layout(pm->n_fft, p.nrb, p.nrbg);
+    L.shl = shift_layout(pm->n_fft, p.nrb_tab, p.nrbg);
     L.sht = o;   o += L.shl.total;
     L.y = o;     o += al(4 * ys);
     L.y64 = o;   if (needs_full_edges(ctx, pm)) o += al(8 * ys);
@@ -1508,7 +1539,7 @@ SearchLayout search_layout(const fh_ctx *ctx, const fh_peakmap *pm, const fh_gri
     const size_t wins = (size_t)8 * c * p.nrbg * p.nbb * win_stride(pm->n_fft);
     SearchLayout L;
     size_t o = 0;
-    L.shl = shift_layout((int64_t)N, p.nrb, p.nrbg);
+    L.shl = shift_layout((int64_t)N, p.nrb_tab, p.nrbg);
     L.sht = o;    o += L.shl.total;
     L.y = o;      o += al(4 * ys * c);
     L.y64 = o;    if (needs_full_edges(ctx, pm)) o += al(8 * ys * c);

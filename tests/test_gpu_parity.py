@@ -145,11 +145,14 @@ def test_random_small_maps_edge_cases(ctx, seed):
     _assert_weighted_close(gotw, refw, wts)
 
 
-@pytest.mark.parametrize("ns,kf", [(1, 10), (2, 1), (5, 10), (6, 37), (7, 10), (17, 10), (21, 2), (22, 10), (38, 10)])
+@pytest.mark.parametrize("ns,kf", [(1, 10), (2, 1), (5, 10), (6, 37), (7, 10), (17, 10), (18, 1), (19, 3), (21, 2),
+                                   (22, 10), (33, 10), (38, 10), (65, 10), (67, 37)])
 def test_short_last_row_block(ctx, ns, kf):
     """Grids whose last 16-row block is partly empty (1 to 15 rows of it
-    exist): maps, weighted maps, candidates of both schedules and column
-    maxima against the oracle."""
+    exist; 1-3 rows after a full block are folded into the tiles of the block
+    before, 65 and 67 rows with the folded rows past a row group): maps,
+    weighted maps, candidates of both schedules and column maxima against the
+    oracle."""
     import torch
     api = _api()
     rng = synth.rng_for(700 + ns * 3 + kf)
@@ -180,6 +183,42 @@ def test_short_last_row_block(ctx, ns, kf):
     top = ref.max(axis=0)
     np.testing.assert_array_equal(val_c.cpu().numpy()[0], top.astype(np.float32))
     np.testing.assert_array_equal(row_c.cpu().numpy()[0], np.argmax(ref == top[None, :], axis=0))
+    dpm.release()
+
+
+@pytest.mark.parametrize("ns", [17, 19, 65])
+def test_folded_tail_rows_equal_a_row_block_of_their_own(ctx, ns):
+    """The same grid with its last 1-3 rows folded into the tiles of the row
+    block before (library-chosen width) and run as a row block of their own
+    (the widest 16-row tile, which leaves no LDS for them): identical
+    candidates and column maxima, and the oracle's."""
+    import torch
+    api = _api()
+    rng = synth.rng_for(900 + ns)
+    print("case: folded tail ns=%d" % ns, flush=True)
+    t_fft = 2048.0
+    pm = synth.random_peakmap(120, t_fft, 60_000, 60_500, 0.08, rng)
+    dfd = (1.0 / t_fft) / (120 * t_fft / 2)
+    grid = synth.Grid(kf=10, b0=10 * 60_020, nf=10 * 450, ns=ns, fdot0=-(ns // 2) * dfd, dfdot=dfd,
+                      t0=float(pm.t[60]))
+    dpm = ctx.upload(pm)
+    folded = ctx.plan(dpm, grid, tile_bins=1280)
+    wide = ctx.plan(dpm, grid, tile_bins=4096)
+    assert folded["n_row_blocks"] == (ns + 15) // 16 - 1, folded
+    assert wide["n_row_blocks"] == (ns + 15) // 16 and wide["tile_bins"] == 2496, wide
+    sky = synth.sky_uniform(5, rng)
+    sel = synth.Selection(width=300)
+    a = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, tile_bins=1280)
+    b = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, tile_bins=4096)
+    va, ra = api.fh_hough_colmax(ctx, dpm, sky, grid, tile_bins=1280)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ref = oracle.hough_map(pm, grid, sky[2])
+    top = ref.max(axis=0)
+    np.testing.assert_array_equal(va.cpu().numpy()[2], top.astype(np.float32))
+    np.testing.assert_array_equal(ra.cpu().numpy()[2], np.argmax(ref == top[None, :], axis=0))
+    idx, val = oracle.candidates(ref, sel.width, sel.excl, sel.sep)
+    _check_candidates(api.decode_candidates(a), 2, idx, val, pm.n_fft, sel.theta)
     dpm.release()
 
 
