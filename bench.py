@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--large-sky", type=int, default=4096,
                     help="directions of the large-band leg (0 disables it)")
     ap.add_argument("--no-probe", action="store_true", help="skip the LDS-atomic probe")
+    ap.add_argument("--shape-sky", type=int, default=128,
+                    help="directions per serving shape timed alone (0 disables the per-shape leg)")
+    ap.add_argument("--shapes-only", nargs="*", default=None,
+                    help="time only the given serving shapes, e.g. 1024:narrow 8192:wide (none = all)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB moved by one plain device copy before the timed steps "
                          "(reference dispatch for hardware byte counters)")
@@ -284,6 +288,57 @@ def build_serving_bands(ctx, f_lo=20, f_hi=1000, seed=77, t_obs_days=149.0):
     return bands
 
 
+SPIN_DOWN_RANGES = {"narrow": (-1e-9, 1e-10), "wide": (-1e-8, 1e-9)}
+
+
+def serving_shapes(ctx, which=None, n_sky=128, reps=3, seed=5):
+    """Each serving shape alone: the first 1 Hz band of each T_FFT with each
+    spin-down range, n_sky random directions, top-2 per 0.1 Hz sub-band.  Per
+    shape: ms per call, the tile kernel's ms and its fraction of the
+    LDS-atomic peak (peaks x rows x directions / tile time / 9.83e12 /s), the
+    front's ms, and the plan (tile width, row blocks run, folded tail rows)."""
+    import torch
+
+    from paper_1407_8333_amd import api, synth
+    bands = build_serving_bands(ctx)
+    first = {}
+    for shape, f, dpm in bands:
+        first.setdefault(shape.t_fft, (shape, f, dpm))
+    rng = synth.rng_for(seed)
+    out = []
+    for t_fft in (8192.0, 4096.0, 2048.0, 1024.0):
+        for name, rg in SPIN_DOWN_RANGES.items():
+            if which and "%d:%s" % (t_fft, name) not in which:
+                continue
+            shape, f, dpm = first[t_fft]
+            grid = synth.make_grid(shape, f, f + 1.0, *rg)
+            sel = synth.Selection(width=int(round(0.1 * grid.kf * t_fft)))
+            sky = synth.sky_uniform(n_sky, rng)
+            api.fh_hough_candidates(ctx, dpm, sky, grid, sel)  # autotunes the shape
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                api.fh_hough_candidates(ctx, dpm, sky, grid, sel)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            pr = ctx.profile_read()
+            ctx.profile(False)
+            plan = ctx.plan(dpm, grid)
+            cells = dpm.n_peaks * grid.ns * n_sky
+            tiles_ms = pr["tiles_ms"] / reps
+            out.append({"t_fft": t_fft, "range": name, "ns": grid.ns, "n_fft": dpm.n_fft,
+                        "n_peaks": dpm.n_peaks, "n_sky": n_sky, "ms": dt * 1e3,
+                        "cell_updates_per_s": cells / dt, "tiles_ms": tiles_ms,
+                        "tile_frac": cells / (tiles_ms * 1e-3) / (LDS_ATOMIC_PEAK_TOPS * 1e12),
+                        "front_ms": pr["front_ms"] / reps, "tile_bins": plan["tile_bins"],
+                        "row_blocks": plan["n_row_blocks"],
+                        "tail_rows": max(0, grid.ns - 16 * plan["n_row_blocks"])})
+    for _, _, dpm in bands:
+        dpm.release()
+    return out
+
+
 def serve_bench(ctx, n_req, load, lanes=8, seed=77, burst_n=192):
     """Poisson stream of (band, sky patch, spin-down range) requests through the
     continuous-batching server.  Bands: one of the 980 resident 1 Hz bands of
@@ -426,6 +481,13 @@ def main():
     import torch
 
     from paper_1407_8333_amd import api, synth
+
+    if args.shapes_only is not None:
+        ctx = api.Context(0)
+        out = {"serving_shapes": serving_shapes(ctx, args.shapes_only, n_sky=args.shape_sky or 128)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
 
     if args.serve_only:
         ctx = api.Context(0)
@@ -587,6 +649,8 @@ def main():
         dpm.release()
         dpm = None
         res["large_band"] = large_band_leg(ctx, args.large_sky)
+    if args.shape_sky > 0 and args.workload == "batch-256hz":
+        res["serving_shapes"] = serving_shapes(ctx, n_sky=args.shape_sky)
     if args.serve_requests > 0:
         res["serving"] = serve_bench(ctx, args.serve_requests, args.serve_load, lanes=args.serve_lanes)
     if not args.no_cpu_baseline:

@@ -606,7 +606,7 @@ fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sk
     cands.push_back(wcap);
     const int w16 = std::min(max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows), wmap);
     if (w16 > wcap) cands.push_back(w16);
-    const int sample = std::min(n_sky, 64);
+    const int sample = std::min(n_sky, 128);
     const bool was = ctx->profiling;
     ctx->profiling = false;
     hipEvent_t e0, e1;
