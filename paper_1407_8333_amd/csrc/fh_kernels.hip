@@ -266,9 +266,10 @@ __global__ void __launch_bounds__(256) k_front(
     uint32_t *__restrict__ Y, const float *__restrict__ w,
     int32_t w_stride, const WeightStats *__restrict__ ws, int32_t ws_stride,
     uint32_t *__restrict__ wq, int32_t ns, int32_t nrbg, int32_t nbb, int32_t W, int32_t F,
-    int2 *__restrict__ win, int32_t shift_mode, double q) {
+    int32_t search_top, int2 *__restrict__ win, int32_t shift_mode, double q) {
     extern __shared__ int64_t ys[];
     __shared__ int64_t s_off[kFrontMaxF + 1];  // offsets of the block's FFTs
+    __shared__ int32_t s_loc[kFrontMaxF + 1];  // the same, from the block's first peak
     __shared__ int64_t s_c[kFrontMaxF];        // per-FFT constant of the edge
     __shared__ double s_r[kFrontMaxF];         // per-FFT inverse Doppler factor
     const int slot = blockIdx.y;
@@ -282,7 +283,11 @@ __global__ void __launch_bounds__(256) k_front(
 
     // per-FFT terms (r, constant, weight), one thread per FFT
     const double *n = sky + 3 * (int64_t)slot;
-    if ((int)threadIdx.x <= nfl) s_off[threadIdx.x] = offsets[f0 + threadIdx.x];
+    if ((int)threadIdx.x <= nfl) {
+        const int64_t o = offsets[f0 + threadIdx.x];
+        s_off[threadIdx.x] = o;
+        s_loc[threadIdx.x] = (int32_t)(o - offsets[f0]);
+    }
     if ((int)threadIdx.x < nfl) {
         const int i = f0 + threadIdx.x;
         const double *vi = v + 3 * (int64_t)i;
@@ -310,29 +315,36 @@ __global__ void __launch_bounds__(256) k_front(
         int l = 0;
         // four peaks per thread and round, their natural bins requested
         // together so that one memory latency covers the round
+        // peak indices local to the block (32-bit: a block holds at most
+        // 48 KB of edges); K_f k < 2^28 (checked at upload), so the natural
+        // frequency in fine bins converts to double from 32 bits exactly
+        const int np = (int)(P1 - P0);
+        const int32_t *__restrict__ kbins = bins + P0;
+        uint32_t *__restrict__ Yb = Yslot + P0 + (int64_t)kYPad * f0;
         constexpr int kU = 4;
-        for (int64_t pb = P0 + threadIdx.x; pb < P1; pb += kU * (int64_t)blockDim.x) {
+        for (int lb = threadIdx.x; lb < np; lb += kU * (int)blockDim.x) {
             int32_t kb[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int64_t p = pb + u * (int64_t)blockDim.x;
-                kb[u] = p < P1 ? bins[p] : 0;
+                const int lp = lb + u * (int)blockDim.x;
+                kb[u] = lp < np ? kbins[lp] : 0;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int64_t p = pb + u * (int64_t)blockDim.x;
-                if (p >= P1) break;
-                while (s_off[l + 1] <= p) ++l;
+                const int lp = lb + u * (int)blockDim.x;
+                if (lp >= np) break;
+                while (s_loc[l + 1] <= lp) ++l;
                 int64_t y;
                 if (shift_mode) {
-                    y = (int64_t)kf * (int64_t)kb[u] * kQ + s_c[l];
+                    y = (int64_t)(kf * kb[u]) * kQ + s_c[l];
                 } else {
-                    double x = (double)((int64_t)kf * (int64_t)kb[u]) * s_r[l];
+                    double x = (double)(kf * kb[u]) * s_r[l];
                     x = x * kQd;
                     y = (int64_t)floor(x) + s_c[l];
                 }
-                Yslot[p + (int64_t)kYPad * (f0 + l)] = (uint32_t)y;  // the tiles use the low word
-                ys[p - P0 + (int64_t)kYPad * l] = y;
+                const int li = lp + kYPad * l;
+                Yb[li] = (uint32_t)y;  // the tiles use the low word
+                ys[li] = y;
             }
         }
         for (int t = threadIdx.x; t < nfl * kYPad; t += blockDim.x) {
@@ -342,37 +354,53 @@ __global__ void __launch_bounds__(256) k_front(
     }
     __syncthreads();
 
-    const int n_entries = nrbg * nbb * F;
-    for (int e = threadIdx.x; e < n_entries; e += blockDim.x) {
-        const int fl = e % F;
-        const int rest = e / F;
-        const int jb = rest % nbb;
-        const int g = rest / nbb;
-        const int f = f0 + fl;
+    // Window entries e = tid + k blockDim, e = (g nbb + jb) F + fl: F divides
+    // blockDim, so a thread keeps one FFT fl, and its row index g nbb + jb
+    // advances by blockDim / F per entry (no division per entry).  Each of
+    // the two searches is a branchless binary lifting over the FFT's staged
+    // edges: powers of two from search_top (the largest power of two up to
+    // the longest FFT's peak count) down to 1, a step taken while the edge
+    // it passes is below the bound.
+    const int fl = (int)threadIdx.x & (F - 1);
+    const int step_r = (int)blockDim.x / F;
+    const int n_rows = nrbg * nbb;
+    int rest = (int)threadIdx.x / F;
+    int g = rest / nbb, jb = rest - g * nbb;
+    const int dg = step_r / nbb, djb = step_r - dg * nbb;
+    const int f = f0 + fl;
+    const bool live = fl < nfl;
+    int a0 = 0, end = 0;
+    if (live) {
+        a0 = s_loc[fl] + kYPad * fl;
+        end = s_loc[fl + 1] + kYPad * fl;
+    }
+    const int64_t *__restrict__ gq = gwin + (int64_t)f * nrbg * 2;
+    int2 *__restrict__ wp = win + (int64_t)slot * n_rows * n_pad + f;
+    for (; rest < n_rows; rest += step_r) {
         int2 out = make_int2(0, 0);
-        if (f < n_fft) {
-            const int64_t p0 = offsets[f] + (int64_t)kYPad * f - pb;
-            const int64_t p1 = offsets[f + 1] + (int64_t)kYPad * f - pb;
+        if (live) {
             // shifts of the group's first and last grid rows
-            const int64_t q_lo = gwin[((int64_t)f * nrbg + g) * 2], q_hi = gwin[((int64_t)f * nrbg + g) * 2 + 1];
+            const int64_t q_lo = gq[2 * g], q_hi = gq[2 * g + 1];
             // max_s a_s = floor((Y - min G) / kQ) >= t  <=>  Y >= t kQ + min G
             // min_s a_s = floor((Y - max G) / kQ) >= t  <=>  Y >= t kQ + max G
             const int64_t y_lo = ((int64_t)jb * W - (kf - 1)) * kQ + (q_lo < q_hi ? q_lo : q_hi);
             const int64_t y_hi = (int64_t)(jb + 1) * W * kQ + (q_lo < q_hi ? q_hi : q_lo);
-            int a = (int)p0, b = (int)p1;
-            while (a < b) {  // first peak with Y >= y_lo
-                const int m = (a + b) >> 1;
-                if (ys[m] >= y_lo) b = m; else a = m + 1;
+            int lo = a0, hi = a0;  // first peaks with Y >= y_lo and with Y >= y_hi
+            for (int stp = search_top; stp > 0; stp >>= 1) {
+                const int t1 = lo + stp - 1, t2 = hi + stp - 1;
+                const int64_t v1 = ys[t1 < end ? t1 : a0], v2 = ys[t2 < end ? t2 : a0];
+                lo += (t1 < end && v1 < y_lo) ? stp : 0;
+                hi += (t2 < end && v2 < y_hi) ? stp : 0;
             }
-            const int lo = a;
-            b = (int)p1;
-            while (a < b) {  // first peak with Y >= y_hi
-                const int m = (a + b) >> 1;
-                if (ys[m] >= y_hi) b = m; else a = m + 1;
-            }
-            out = make_int2((int)(lo + pb), (int)(a + pb));
+            out = make_int2((int)(lo + pb), (int)(hi + pb));
         }
-        win[(((int64_t)slot * nrbg + g) * nbb + jb) * n_pad + f] = out;
+        wp[(int64_t)rest * n_pad] = out;
+        g += dg;
+        jb += djb;
+        if (jb >= nbb) {
+            jb -= nbb;
+            ++g;
+        }
     }
 }
 
@@ -1620,8 +1648,10 @@ hipError_t launch_front(int32_t n_fft, int64_t n_peaks, const int64_t *offsets, 
     dim3 grid(win_stride(n_fft) / F, n_slots);
     const size_t lds = ((size_t)F * (max_per_fft + kYPad) * 8 + 255) / 256 * 256;
     if (F > kFrontMaxF || lds > (size_t)kFrontLdsBytes) return hipErrorInvalidValue;
+    int32_t top = 0;  // largest power of two up to max_per_fft (0 when no FFT has a peak)
+    while (top * 2 <= max_per_fft && top < (1 << 30)) top = top ? 2 * top : 1;
     k_front<<<grid, 256, lds, st>>>(n_fft, n_peaks, offsets, bins, v, sky, kf, b0, gwin, Y,
-                                               w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, win,
+                                               w, w_stride, ws, ws_stride, wq, ns, nrbg, nbb, W, F, top, win,
                                                shift_mode, q);
     return hipGetLastError();
 }
