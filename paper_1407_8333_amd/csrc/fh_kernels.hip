@@ -1201,8 +1201,9 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         Q.pk = (int)w2[1];
     };
     // stripe edges, row terms and weights of block bb (stage 2): the chunk
-    // sizes follow the largest window of the four groups, group 0's (the runs
-    // are sorted by window size).  The row term of row s0 + j,
+    // sizes follow the largest window of the four groups (the runs are sorted
+    // by window size, but only sizes below 127 exactly, so the maximum is
+    // taken over the four).  The row term of row s0 + j,
     // G_{i,s0} - G_{i,s0+j} = 1 - step[i][j] - code_j (mod 2^32), comes from the
     // FFT's step table and the row block's record (the host keeps N nrb below
     // 2^28, so the byte offsets fit 31 bits).
@@ -1225,7 +1226,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             Q.tt = Q.t + code - code2 + (Q.gb - (uint32_t)r2[0]);
         }
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
-        Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
+        Q.cmax = max(max(__builtin_amdgcn_readlane(Q.cnt, 0), __builtin_amdgcn_readlane(Q.cnt, 16)),
+                     max(__builtin_amdgcn_readlane(Q.cnt, 32), __builtin_amdgcn_readlane(Q.cnt, 48)));
         const int n1 = min(Q.cmax, 16);
         const int n2 = min(max(Q.cmax - 16, 0), 16);
         Q.m1 = __builtin_amdgcn_readlane(mtab, n1);
