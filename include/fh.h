@@ -27,8 +27,11 @@
  *   Rejected with FH_E_UNSUPPORTED: a grid whose largest step
  *   |dfdot tau_i| K_f T_FFT reaches 128 fine bins per row (the tiles keep
  *   tile-relative stripe edges in 32 bits), a peakmap with an FFT of 65536
- *   peaks or more, and n_fft * ceil(ns / 16) reaching 2^28 (the per-row
- *   shift records are addressed with 31-bit byte offsets).
+ *   peaks or more, n_fft * ceil(ns / 16) reaching 2^28 (the per-row shift
+ *   records are addressed with 31-bit byte offsets), n_fft above
+ *   524 160 (a tile run of every 16th FFT holds at most 32767), and
+ *   n_peaks + 16 n_fft reaching 2^30 (a direction's stripe edges are
+ *   addressed with 32-bit byte offsets).
  *
  * Conventions
  *   - Every pointer named d_* is device memory on the context's device and is

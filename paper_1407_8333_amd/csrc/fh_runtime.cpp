@@ -285,6 +285,12 @@ fh_status check_grid(const fh_peakmap *pm, const fh_grid *g) {
     if (!(gmax < 1e12)) return fail(FH_E_INVALID, "spin-down shifts exceed the fixed-point range");
     if (pm->max_per_fft >= 65536)
         return fail(FH_E_UNSUPPORTED, "an FFT holds %d peaks; at most 65535 are supported", pm->max_per_fft);
+    // a window entry holds its FFT's place in a tile run in 15 bits, and the
+    // tiles address a direction's stripe edges with 32-bit byte offsets
+    if (wave_ffts(pm->n_fft) >= 32768)
+        return fail(FH_E_UNSUPPORTED, "n_fft=%d: a tile run would hold more than 32767 FFTs", pm->n_fft);
+    if (y_stride(pm->n_peaks, pm->n_fft) >= ((int64_t)1 << 30))
+        return fail(FH_E_UNSUPPORTED, "n_peaks + 16 n_fft reaches 2^30");
     // the tiles address the shift records [row blocks][N] with 31-bit byte offsets
     const int64_t nrb = (int64_t)(g->ns + kTileRows - 1) / kTileRows;
     if ((int64_t)pm->n_fft * nrb >= ((int64_t)1 << 28))

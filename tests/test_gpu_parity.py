@@ -256,6 +256,25 @@ def test_windows_of_more_than_127_peaks(ctx):
     dpm.release()
 
 
+def test_fft_count_limit_of_the_tile_runs(ctx):
+    """A tile run holds every 16th FFT, its place in 15 bits: 524 160 FFTs are
+    searched, one more is refused with FH_E_UNSUPPORTED (the peakmaps have no
+    peaks; only the plan is asked for)."""
+    from paper_1407_8333_amd import _lib
+    for n_fft, ok in ((524_160, True), (524_161, False)):
+        t = synth.fft_times(n_fft, 1024.0)
+        pm = synth.Peakmap(1024.0, t, np.zeros((n_fft, 3)), np.zeros(n_fft + 1, np.int64), np.zeros(0, np.int32))
+        grid = synth.Grid(kf=10, b0=10 * 60_000, nf=1000, ns=4, fdot0=0.0, dfdot=1e-12, t0=float(t[n_fft // 2]))
+        dpm = ctx.upload(pm)
+        if ok:
+            assert ctx.plan(dpm, grid)["n_row_blocks"] == 1
+        else:
+            with pytest.raises(_lib.FHError) as e:
+                ctx.plan(dpm, grid)
+            assert e.value.status == _lib.FH_E_UNSUPPORTED
+        dpm.release()
+
+
 def test_zero_peaks_gives_zero_map(ctx):
     t = synth.fft_times(5, 1024.0)
     pm = synth.Peakmap(1024.0, t, np.zeros((5, 3)), np.zeros(6, np.int64), np.zeros(0, np.int32))
