@@ -528,14 +528,32 @@ __global__ void __launch_bounds__(256) k_windows_sweep(
 // kTileWaves-th FFT, w, w + 16, w + 32, ... (so that every run spans the
 // whole observation, whose windows widen with |t - t0|); its wave_ffts(N)
 // FFTs are sorted by window size, largest first (a counting sort over sizes
-// clipped to 127), so that the four FFTs of a tile block (four consecutive
-// entries of a run) have nearly equal windows.  An entry becomes
+// clipped to 127; the few windows of 127 peaks or more, which share the first
+// bucket, are ranked exactly among themselves), so that the four FFTs of a
+// tile block (four consecutive entries of a run) have nearly equal windows
+// and the first holds the largest, which the tiles rely on.  An entry becomes
 // (lo, m << 16 | count): FFT m * 16 + w of the row.  One workgroup per window
 // row (grid.x = row group * bin blocks, grid.y = slot), one wave per run.
 constexpr int kSortBuckets = 128;
 // rows of at most this many bytes are first copied into LDS with 16-byte
 // loads (the runs read the row with a 128-byte stride, twice)
 constexpr int kSortStageBytes = 128 * 1024;
+
+// Place of a window of c >= 127 peaks (entry e of a run of `per`) among the
+// run's windows of 127 peaks or more, which fill the run's first places:
+// larger first, equal sizes in run order.  entry(j) reads entry j of the run.
+// Such windows are rare (dense peakmaps, K_f = 1), so a scan of the run is
+// cheap enough.
+template <typename Entry>
+__device__ __forceinline__ int big_window_rank(int c, int e, int per, Entry entry) {
+    int pos = 0;
+    for (int j = 0; j < per; ++j) {
+        const int2 o = entry(j);
+        const int cj = o.y - o.x;
+        pos += (cj > c || (cj == c && j < e)) ? 1 : 0;
+    }
+    return pos;
+}
 
 __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, int32_t nrows,
                                                                const int2 *__restrict__ win,
@@ -595,7 +613,12 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows(int32_t n_fft, in
             const int e = e0 + 64 * u;
             if (e >= per) break;
             const int c = w2[u].y - w2[u].x;
-            const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
+            int pos;
+            if (c >= kSortBuckets - 1) {
+                pos = big_window_rank(c, e, per, [&](int j) { return src[(int64_t)j * kTileWaves]; });
+            } else {
+                pos = atomicAdd(&h[kSortBuckets - 1 - c], 1);
+            }
             dst[pos] = make_int2(w2[u].x, (e << 16) | c);
         }
     }
@@ -679,7 +702,13 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_windows_long(int32_t n_ff
                 const int e = e0 + 64 * u;
                 if (e >= e_hi) break;
                 const int c = w2[u].y - w2[u].x;
-                const int pos = atomicAdd(&h[kSortBuckets - 1 - min(c, kSortBuckets - 1)], 1);
+                int pos;
+                if (c >= kSortBuckets - 1) {
+                    // the run's other pieces are not staged: read the row in memory
+                    pos = big_window_rank(c, e, per, [&](int j) { return rowp[(int64_t)j * kTileWaves + wave]; });
+                } else {
+                    pos = atomicAdd(&h[kSortBuckets - 1 - c], 1);
+                }
                 dst[pos] = make_int2(w2[u].x, (e << 16) | c);
             }
         }
@@ -1201,9 +1230,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
         Q.pk = (int)w2[1];
     };
     // stripe edges, row terms and weights of block bb (stage 2): the chunk
-    // sizes follow the largest window of the four groups (the runs are sorted
-    // by window size, but only sizes below 127 exactly, so the maximum is
-    // taken over the four).  The row term of row s0 + j,
+    // sizes follow the largest window of the four groups, group 0's (the runs
+    // are sorted by window size, exactly).  The row term of row s0 + j,
     // G_{i,s0} - G_{i,s0+j} = 1 - step[i][j] - code_j (mod 2^32), comes from the
     // FFT's step table and the row block's record (the host keeps N nrb below
     // 2^28, so the byte offsets fit 31 bits).
@@ -1226,8 +1254,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &A, uint32_t *__restric
             Q.tt = Q.t + code - code2 + (Q.gb - (uint32_t)r2[0]);
         }
         Q.wq = WEIGHTED ? ld_u32(B.wq, fc * 4u) : 1u;
-        Q.cmax = max(max(__builtin_amdgcn_readlane(Q.cnt, 0), __builtin_amdgcn_readlane(Q.cnt, 16)),
-                     max(__builtin_amdgcn_readlane(Q.cnt, 32), __builtin_amdgcn_readlane(Q.cnt, 48)));
+        Q.cmax = __builtin_amdgcn_readlane(Q.cnt, 0);
         const int n1 = min(Q.cmax, 16);
         const int n2 = min(max(Q.cmax - 16, 0), 16);
         Q.m1 = __builtin_amdgcn_readlane(mtab, n1);

@@ -542,11 +542,16 @@ fh_status enqueue_map(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const
 // chunk: as many directions as a 48 GiB workspace holds (a sixth of the
 // MI355X's HBM), at most 4096: fewer launches, more tiles per persistent
 // launch (the 256 Hz batch of 1024 directions, 27 GB, is one launch)
+// Directions whose tiles one launch can number (tile ids are 32-bit).
+int64_t chunk_by_tiles(const Plan &p) {
+    return std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / std::max<int64_t>(1, p.tiles_per_sky));
+}
+
 int default_chunk(const fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, const Plan &p, int requested) {
-    if (requested > 0) return requested;
+    if (requested > 0) return (int)std::min<int64_t>(requested, chunk_by_tiles(p));
     const int64_t per_sky = edge_bytes_per_sky(ctx, pm) + 16 * (int64_t)p.nrbg * p.nbb * win_stride(pm->n_fft) + 8 * (int64_t)g->nf;
     const int64_t by_mem = std::max<int64_t>(1, ((int64_t)48 << 30) / std::max<int64_t>(1, per_sky));
-    return (int)std::min<int64_t>(by_mem, 4096);
+    return (int)std::min<int64_t>(std::min<int64_t>(by_mem, 4096), chunk_by_tiles(p));
 }
 
 // Enqueue the search of n_sky directions (already uploaded to b.sky) in
@@ -1778,7 +1783,7 @@ fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id) 
     // the largest chunk whose footprint fits one lane's share of the budget
     const bool weighted = req->d_w != nullptr;
     const int64_t share = srv->budget / (int64_t)srv->lanes.size();
-    int chunk = std::min<int>(req->n_sky, 256);
+    int chunk = (int)std::min<int64_t>(std::min<int>(req->n_sky, 256), chunk_by_tiles(p));
     while (chunk > 1 &&
            (int64_t)search_layout(ctx, req->pm, &req->grid, p, chunk, req->n_sky, weighted).total > share)
         chunk = (chunk + 1) / 2;

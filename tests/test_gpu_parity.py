@@ -222,33 +222,35 @@ def test_folded_tail_rows_equal_a_row_block_of_their_own(ctx, ns):
     dpm.release()
 
 
-def test_windows_of_more_than_127_peaks(ctx):
-    """K_f = 1 with the widest tile: windows of several hundred peaks, beyond
-    the sizes that the window sort orders exactly (from 127 peaks up they
-    share one bucket), so a block's largest window need not come first:
-    maps, weighted maps and candidates of both schedules against the
-    oracle."""
+@pytest.mark.parametrize("n_fft,n_bins,nf,ns", [(48, 6000, 5600, 20), (16_500, 1000, 900, 4)])
+def test_windows_of_more_than_127_peaks(ctx, n_fft, n_bins, nf, ns):
+    """K_f = 1 with the widest tile: windows of hundreds of peaks, beyond the
+    sizes that the window sort's counting buckets order (from 127 peaks up
+    they share one bucket, ranked apart; with 16 500 FFTs the rows are sorted
+    in pieces): maps, weighted maps and candidates of both schedules against
+    the oracle."""
     import torch
     api = _api()
-    rng = synth.rng_for(1270)
-    print("case: windows of more than 127 peaks", flush=True)
+    rng = synth.rng_for(1270 + n_fft)
+    print("case: windows of more than 127 peaks, %d FFTs" % n_fft, flush=True)
     t_fft = 1024.0
-    pm = synth.random_peakmap(48, t_fft, 60_000, 66_000, 0.3, rng)
-    assert np.diff(pm.offsets).max() > 1000
-    dfd = (1.0 / t_fft) / (48 * t_fft / 2)
-    grid = synth.Grid(kf=1, b0=60_200, nf=5_600, ns=20, fdot0=-10 * dfd, dfdot=dfd, t0=float(pm.t[24]))
+    pm = synth.random_peakmap(n_fft, t_fft, 60_000, 60_000 + n_bins, 0.3, rng)
+    assert np.diff(pm.offsets).min() > 127
+    dfd = (1.0 / t_fft) / (n_fft * t_fft / 2)
+    grid = synth.Grid(kf=1, b0=60_000 + (n_bins - nf) // 2, nf=nf, ns=ns, fdot0=-(ns // 2) * dfd, dfdot=dfd,
+                      t0=float(pm.t[n_fft // 2]))
     nhat = synth.sky_uniform(1, rng)[0]
     dpm = ctx.upload(pm)
-    assert ctx.plan(dpm, grid)["tile_bins"] == 2496
+    assert ctx.plan(dpm, grid)["tile_bins"] >= min(nf, 2496)
     ref = oracle.hough_map(pm, grid, nhat)
     np.testing.assert_array_equal(_gpu_map(ctx, pm, grid, nhat), ref.astype(np.int32))
     wts = rng.uniform(0.5, 1.5, pm.n_fft).astype(np.float32)
     refw = oracle.hough_map(pm, grid, nhat, weights=wts.astype(np.float64))
     _assert_weighted_close(_gpu_map(ctx, pm, grid, nhat, weights=wts), refw, wts)
     sky = np.concatenate([nhat[None, :], synth.sky_uniform(3, rng)])
-    sel = synth.Selection(width=700)
-    raw_p = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=1, tile_bins=2496)
-    raw_0 = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=0, tile_bins=2496)
+    sel = synth.Selection(width=max(1, nf // 8))
+    raw_p = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=1, tile_bins=nf)
+    raw_0 = api.fh_hough_candidates(ctx, dpm, sky, grid, sel, schedule=0, tile_bins=nf)
     torch.cuda.synchronize()
     assert torch.equal(raw_p, raw_0)
     idx, val = oracle.candidates(ref, sel.width, sel.excl, sel.sep)
