@@ -776,11 +776,13 @@ __device__ __forceinline__ void stripe_run(uint32_t v, uint32_t t, uint32_t dump
     }
 }
 
-// A chunk of up to 64 peaks of one FFT occupies the lanes named by a 16-bit
-// pattern m(n), n = ceil(peaks / 4), built from fixed runs so that each run
-// is one straight sequence of steps: lanes 0-7 (n & 8), 8-11 (n & 4),
-// 12-13 (n & 2), 14 (n & 1); n = 16 uses all 16.  Lane j of every group
-// holds peak 4 q + g, q = the number of pattern lanes below j.
+// A chunk of up to 16 peaks of each group's FFT occupies the lanes named by
+// a 16-bit pattern m(n), n = min(peaks left in the block's largest window,
+// 16), built from fixed runs so that each run is one straight sequence of
+// steps: lanes 0-7 (n & 8), 8-11 (n & 4), 12-13 (n & 2), 14 (n & 1); n = 16
+// uses all 16.  Pattern lane j of a group holds its FFT's peak q (plus the
+// chunk's first peak), q = the number of pattern lanes below j; lanes
+// outside the pattern take part in the steps only as rows.
 __device__ __forceinline__ uint32_t chunk_pattern(int n) {
     if (n >= 16) return 0xFFFFu;
     return ((1u << (n & 8)) - 1u) | (((1u << (n & 4)) - 1u) << 8) |
