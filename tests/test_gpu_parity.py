@@ -258,6 +258,43 @@ def test_windows_of_more_than_127_peaks(ctx, n_fft, n_bins, nf, ns):
     dpm.release()
 
 
+@pytest.mark.parametrize("sign,ns", [(-1.0, 19), (-1.0, 40), (0.0, 17), (0.0, 3)])
+def test_descending_and_flat_spin_down_rows(ctx, sign, ns):
+    """Rows whose spin-down decreases (dfdot < 0, the row terms change sign)
+    and rows that all coincide (dfdot = 0: every row equals row 0, so the
+    column maxima pick row 0 on the ties), with and without folded tail
+    rows: maps, weighted maps, candidates and column maxima against the
+    oracle."""
+    import torch
+    api = _api()
+    rng = synth.rng_for(3300 + ns + int(sign))
+    print("case: dfdot sign %g, %d rows" % (sign, ns), flush=True)
+    t_fft = 2048.0
+    pm = synth.random_peakmap(80, t_fft, 70_000, 70_500, 0.08, rng)
+    dfd = sign * (1.0 / t_fft) / (80 * t_fft / 2)
+    grid = synth.Grid(kf=10, b0=10 * 70_050, nf=10 * 400, ns=ns, fdot0=(ns // 2) * abs(dfd), dfdot=dfd,
+                      t0=float(pm.t[20]))
+    nhat = synth.sky_uniform(1, rng)[0]
+    ref = oracle.hough_map(pm, grid, nhat)
+    np.testing.assert_array_equal(_gpu_map(ctx, pm, grid, nhat), ref.astype(np.int32))
+    wts = rng.uniform(0.5, 1.5, pm.n_fft).astype(np.float32)
+    _assert_weighted_close(_gpu_map(ctx, pm, grid, nhat, weights=wts),
+                           oracle.hough_map(pm, grid, nhat, weights=wts.astype(np.float64)), wts)
+    dpm = ctx.upload(pm)
+    sel = synth.Selection(width=500)
+    raw = api.fh_hough_candidates(ctx, dpm, nhat[None, :], grid, sel, tile_bins=1280)
+    val_c, row_c = api.fh_hough_colmax(ctx, dpm, nhat[None, :], grid, tile_bins=1280)
+    torch.cuda.synchronize()
+    idx, val = oracle.candidates(ref, sel.width, sel.excl, sel.sep)
+    _check_candidates(api.decode_candidates(raw), 0, idx, val, pm.n_fft, sel.theta)
+    top = ref.max(axis=0)
+    np.testing.assert_array_equal(val_c.cpu().numpy()[0], top.astype(np.float32))
+    np.testing.assert_array_equal(row_c.cpu().numpy()[0], np.argmax(ref == top[None, :], axis=0))
+    if sign == 0.0:
+        assert (row_c.cpu().numpy()[0] == 0).all()
+    dpm.release()
+
+
 def test_fft_count_limit_of_the_tile_runs(ctx):
     """A tile run holds every 16th FFT, its place in 15 bits: 524 160 FFTs are
     searched, one more is refused with FH_E_UNSUPPORTED (the peakmaps have no
