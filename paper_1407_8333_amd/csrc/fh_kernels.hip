@@ -308,43 +308,45 @@ __global__ void __launch_bounds__(256) k_front(
     }
     __syncthreads();
 
-    // stripe edges (as k_prep) of all the block's peaks, spread over every
-    // thread; the FFT of a peak advances monotonically per thread
+    // stripe edges (as k_prep) of all the block's peaks: wave w takes FFTs w,
+    // w + 4, ..., its lanes that FFT's consecutive peaks, so no lane searches
+    // for its FFT and its Doppler factor and constant are read once per FFT
     if (nfl > 0) {
-        const int64_t P0 = s_off[0], P1 = s_off[nfl];
-        int l = 0;
-        // four peaks per thread and round, their natural bins requested
-        // together so that one memory latency covers the round
+        const int64_t P0 = s_off[0];
         // peak indices local to the block (32-bit: a block holds at most
         // 48 KB of edges); K_f k < 2^28 (checked at upload), so the natural
         // frequency in fine bins converts to double from 32 bits exactly
-        const int np = (int)(P1 - P0);
         const int32_t *__restrict__ kbins = bins + P0;
         uint32_t *__restrict__ Yb = Yslot + P0 + (int64_t)kYPad * f0;
-        constexpr int kU = 4;
-        for (int lb = threadIdx.x; lb < np; lb += kU * (int)blockDim.x) {
-            int32_t kb[kU];
+        const int lane = (int)threadIdx.x & 63, nw = (int)blockDim.x >> 6;
+        constexpr int kU = 4;  // peaks per lane and round, their natural bins requested together
+        for (int l = (int)threadIdx.x >> 6; l < nfl; l += nw) {
+            const int pa = s_loc[l], pe = s_loc[l + 1];
+            const double r = s_r[l];
+            const int64_t c = s_c[l];
+            for (int lb = pa + lane; lb < pe; lb += 64 * kU) {
+                int32_t kb[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int lp = lb + u * (int)blockDim.x;
-                kb[u] = lp < np ? kbins[lp] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int lp = lb + u * (int)blockDim.x;
-                if (lp >= np) break;
-                while (s_loc[l + 1] <= lp) ++l;
-                int64_t y;
-                if (shift_mode) {
-                    y = (int64_t)(kf * kb[u]) * kQ + s_c[l];
-                } else {
-                    double x = (double)(kf * kb[u]) * s_r[l];
-                    x = x * kQd;
-                    y = (int64_t)floor(x) + s_c[l];
+                for (int u = 0; u < kU; ++u) {
+                    const int lp = lb + 64 * u;
+                    kb[u] = lp < pe ? kbins[lp] : 0;
                 }
-                const int li = lp + kYPad * l;
-                Yb[li] = (uint32_t)y;  // the tiles use the low word
-                ys[li] = y;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int lp = lb + 64 * u;
+                    if (lp >= pe) break;
+                    int64_t y;
+                    if (shift_mode) {
+                        y = (int64_t)(kf * kb[u]) * kQ + c;
+                    } else {
+                        double x = (double)(kf * kb[u]) * r;
+                        x = x * kQd;
+                        y = (int64_t)floor(x) + c;
+                    }
+                    const int li = lp + kYPad * l;
+                    Yb[li] = (uint32_t)y;  // the tiles use the low word
+                    ys[li] = y;
+                }
             }
         }
         for (int t = threadIdx.x; t < nfl * kYPad; t += blockDim.x) {
