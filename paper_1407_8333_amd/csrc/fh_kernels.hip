@@ -1000,11 +1000,41 @@ __device__ __forceinline__ void tile_output(const TileArgs &A, int slot, int rb,
 // phases (the caller's prefetch of the next tile); the caller's barrier then
 // separates the clearing from the next tile's updates.
 constexpr int kHold = 9;  // held columns per lane: K_f - 1 <= kHold
+constexpr int kRound = 8;  // columns per round of the first output phase
+
+// The whole rounds of the first phase from column x of a segment ending at
+// x1: window sums written in place, with no test per column; MASK writes
+// zeros for a row past the grid (only the last row block has such rows).
+// Returns the first column not done (fewer than kRound remain).
+template <bool MASK>
+__device__ __forceinline__ int colmax_rounds(uint32_t *__restrict__ P, int x, int x1, int kf,
+                                             uint32_t &acc, bool row_ok) {
+    for (; x + kRound <= x1; x += kRound) {
+        const uint32_t *ph = P + (x + kf - 1) * kTileRows;
+        uint32_t *pt = P + x * kTileRows;
+        uint32_t h[kRound], t[kRound], o[kRound];
+#pragma unroll
+        for (int c = 0; c < kRound; ++c) {
+            h[c] = ph[c * kTileRows];
+            t[c] = pt[c * kTileRows];
+        }
+#pragma unroll
+        for (int c = 0; c < kRound; ++c) {
+            acc += h[c];
+            o[c] = MASK && !row_ok ? 0u : acc;
+            acc -= t[c];
+        }
+        // a round's writes follow all of its reads: column x + c is read as a
+        // head by earlier rounds only, and as a trail by this round
+#pragma unroll
+        for (int c = 0; c < kRound; ++c) pt[c * kTileRows] = o[c];
+    }
+    return x;
+}
 
 template <typename Mid>
 __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb, int jb,
                                             uint32_t *__restrict__ lds, Mid mid) {
-    constexpr int kB = 8;  // columns per round
     const int tid = threadIdx.x;
     const int j = tid & 15;
     const int W = A.W, kf = A.kf;
@@ -1044,35 +1074,25 @@ __device__ __forceinline__ void tile_colmax(const TileArgs &A, int slot, int rb,
             if (c < nh) acc = v - t[c];
         }
     }
-    for (int x = x0 + nh; x < x1; x += kB) {
-        const bool full = x + kB <= x1;
-        uint32_t h[kB], t[kB], o[kB];
-        if (full) {
-            const uint32_t *ph = P + (x + kf - 1) * kTileRows;
-            const uint32_t *pt = P + x * kTileRows;
+    int x = x0 + nh;
+    if (s0 + kTileRows <= A.ns) x = colmax_rounds<false>(P, x, x1, kf, acc, true);
+    else x = colmax_rounds<true>(P, x, x1, kf, acc, row_ok);
+    if (x < x1) {  // the segment's last, partial round
+        uint32_t h[kRound], t[kRound], o[kRound];
 #pragma unroll
-            for (int c = 0; c < kB; ++c) {
-                h[c] = ph[c * kTileRows];
-                t[c] = pt[c * kTileRows];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kB; ++c) {
-                const int xc = min(x + c, x1 - 1);
-                h[c] = P[(xc + kf - 1) * kTileRows];
-                t[c] = P[xc * kTileRows];
-            }
+        for (int c = 0; c < kRound; ++c) {
+            const int xc = min(x + c, x1 - 1);
+            h[c] = P[(xc + kf - 1) * kTileRows];
+            t[c] = P[xc * kTileRows];
         }
 #pragma unroll
-        for (int c = 0; c < kB; ++c) {
+        for (int c = 0; c < kRound; ++c) {
             acc += h[c];
             o[c] = row_ok ? acc : 0u;
             acc -= t[c];
         }
-        // a round's writes follow all of its reads: column x + c is read as a
-        // head by earlier rounds only, and as a trail by this round
 #pragma unroll
-        for (int c = 0; c < kB; ++c)
+        for (int c = 0; c < kRound; ++c)
             if (x + c < x1) P[(x + c) * kTileRows] = o[c];
     }
     mid();
