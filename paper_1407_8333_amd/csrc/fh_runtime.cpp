@@ -176,8 +176,9 @@ struct fh_ctx {
     DevBuf rf_offsets, rf_bins, rf_t, rf_v, rf_first, rf_counts, rf_cands, rf_aux;
     // cleaning: robust-statistic histogram, its rank sum and results
     DevBuf cl_hist, cl_s2, cl_out;
-    // autotuned tile width per problem shape
-    std::map<std::tuple<int, int, int, int, int>, int> tuned;
+    // autotuned tile width per problem shape (shared by weighted and
+    // unweighted searches: the two kernels differ only in the added value)
+    std::map<std::tuple<int, int, int, int>, int> tuned;
     // captured searches (fh_options.use_graph), keyed by every argument and
     // workspace pointer they bake in
     struct GraphEntry {
@@ -310,20 +311,19 @@ fh_status check_sky(const double *n) {
     return FH_OK;
 }
 
-std::tuple<int, int, int, int, int> tune_key(const fh_peakmap *pm, const fh_grid *g, bool weighted) {
-    return std::make_tuple(pm->n_fft, g->nf, g->ns, g->kf, weighted ? 1 : 0);
+std::tuple<int, int, int, int> tune_key(const fh_peakmap *pm, const fh_grid *g) {
+    return std::make_tuple(pm->n_fft, g->nf, g->ns, g->kf);
 }
 
 // Tile width: the requested one (multiple of 64, at most what a 16-row tile
 // holds; a width too wide for the tail rows runs them as a row block of
 // their own), else the autotuned one, else the widest that also holds the
 // tail rows.
-int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested,
-                     bool weighted = false) {
+int choose_tile_bins(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int requested) {
     const int wmax = tile_bins_limit(pm, g);
     if (requested > 0)
         return std::min(((requested + 63) / 64) * 64, max_tile_bins(g->kf, row_step_bins(pm, g), kTileRows));
-    auto it = ctx->tuned.find(tune_key(pm, g, weighted));
+    auto it = ctx->tuned.find(tune_key(pm, g));
     if (it != ctx->tuned.end()) return it->second;
     // a tile never needs to be wider than the map
     int w = std::min(wmax, ((g->nf + 63) / 64) * 64);
@@ -653,7 +653,7 @@ fh_status autotune(fh_ctx *ctx, const fh_peakmap *pm, const fh_grid *g, int n_sk
     (void)hipEventDestroy(e1);
     ctx->profiling = was;
     if (s) return s;
-    ctx->tuned[tune_key(pm, g, weighted)] = best_w;
+    ctx->tuned[tune_key(pm, g)] = best_w;
     return FH_OK;
 }
 
@@ -1130,7 +1130,7 @@ fh_status fh_refine(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_cand, const fh_
     HIP_OK(hipMemcpyAsync(sub.d_t, pm->d_t, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(sub.d_v, pm->d_v, 24 * (size_t)N, hipMemcpyDeviceToDevice, st));
     const bool weighted = d_w != nullptr;
-    const Plan p = make_plan(grids[0], choose_tile_bins(ctx, &sub, &grids[0], 0, weighted));
+    const Plan p = make_plan(grids[0], choose_tile_bins(ctx, &sub, &grids[0], 0));
     ChunkBufs b;
     if ((s = ensure_workspace(ctx, &sub, &grids[0], p, n_dir, n_cand * n_dir, weighted, st, b))) return s;
     if ((s = upload_sky(ctx, sky.data(), n_cand * n_dir, b, st))) return s;
@@ -1391,9 +1391,9 @@ fh_status fh_hough_candidates(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, 
     if (o.tile_bins < 0 || o.sky_chunk < 0) return fail(FH_E_INVALID, "negative option");
     hipStream_t st = (hipStream_t)stream;
     const bool weighted = d_w != nullptr;
-    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g, weighted)) == ctx->tuned.end())
+    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g)) == ctx->tuned.end())
         if ((s = autotune(ctx, pm, g, n_sky, sky, d_w, w_stride, st))) return s;
-    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins, weighted));
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins));
     int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(ctx, pm, g, p, o.sky_chunk);
     chunk = std::min(chunk, n_sky);
     ChunkBufs b;
@@ -1476,9 +1476,9 @@ fh_status fh_hough_colmax(fh_ctx *ctx, const fh_peakmap *pm, int32_t n_sky, cons
     if (o.tile_bins < 0 || o.sky_chunk < 0) return fail(FH_E_INVALID, "negative option");
     hipStream_t st = (hipStream_t)stream;
     const bool weighted = d_w != nullptr;
-    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g, weighted)) == ctx->tuned.end())
+    if (o.tile_bins == 0 && ctx->tuned.find(tune_key(pm, g)) == ctx->tuned.end())
         if ((s = autotune(ctx, pm, g, n_sky, sky, d_w, w_stride, st))) return s;
-    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins, weighted));
+    const Plan p = make_plan(*g, choose_tile_bins(ctx, pm, g, o.tile_bins));
     int chunk = o.schedule == FH_SCHED_PLAIN ? 1 : default_chunk(ctx, pm, g, p, o.sky_chunk);
     chunk = std::min(chunk, n_sky);
     ChunkBufs b;
@@ -1778,7 +1778,7 @@ fh_status fh_server_submit(fh_server *srv, const fh_request *req, uint64_t *id) 
     R.sky.assign(req->sky, req->sky + 3 * (int64_t)req->n_sky);
     R.r.sky = nullptr;
     R.t_submit = Clock::now();
-    R.W = choose_tile_bins(ctx, req->pm, &req->grid, 0, req->d_w != nullptr);
+    R.W = choose_tile_bins(ctx, req->pm, &req->grid, 0);
     const Plan p = make_plan(req->grid, R.W);
     // the largest chunk whose footprint fits one lane's share of the budget
     const bool weighted = req->d_w != nullptr;
