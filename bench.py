@@ -366,13 +366,14 @@ def serve_bench(ctx, n_req, load, lanes=8, seed=77, burst_n=192):
     def out_for(r):
         return torch.empty((len(r[3]), api.n_subbands(r[1], r[2]), 2, 8), dtype=torch.int32, device="cuda")
 
-    # one search per distinct shape first (T_FFT x spin-down range): tile autotuning
+    # one search per distinct shape first (T_FFT x spin-down range): tile
+    # autotuning on 128 directions, as the serving_shapes leg tunes them
     for t_fft in (8192.0, 4096.0, 2048.0, 1024.0):
         shape, f_lo, dpm = next(b for b in bands if b[0].t_fft == t_fft)
         for rg in ranges:
             grid = synth.make_grid(shape, f_lo, f_lo + 1.0, *rg)
             sel = synth.Selection(width=int(round(0.1 * grid.kf * t_fft)))
-            api.fh_hough_candidates(ctx, dpm, synth.sky_uniform(16, rng), grid, sel)
+            api.fh_hough_candidates(ctx, dpm, synth.sky_uniform(128, rng), grid, sel)
     torch.cuda.synchronize()
 
     srv = api.Server(ctx, hbm_budget=64 << 30, lanes=lanes)
