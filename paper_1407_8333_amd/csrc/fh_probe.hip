@@ -19,6 +19,9 @@
 //   5  the tile pattern with slanted stripes: lane j of a group hits column
 //      c + floor(j s / 8) with a slope s in [-40, 40] / 8 columns per row
 //      drawn per group, as a stripe crosses the 16 rows of a tile
+//   6  the tile pattern with only lanes 0-2 of each group active (a row
+//      block with 3 rows on the grid): 12 of 64 lanes per atomic, to show
+//      whether the pipe's cost follows the active lanes or the instructions
 // Cycles come from the shader clock (clock64) around the loop, between two
 // workgroup barriers, and the same interval on the constant 100 MHz clock
 // (wall_clock64) gives the shader clock's frequency under this load; the
@@ -63,8 +66,8 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
             const int slope8 = (int)(hh >> 16) % 81 - 40;
             const int col = (int)(hh % 1024u) + 512 + ((lane & 15) * slope8 >> 3);
             w = (uint32_t)col * 16u + (uint32_t)(lane & 15);
-        } else if (mode == 2 || mode == 4) {
-            const uint32_t kk = mode == 2 ? (uint32_t)k : 0u;
+        } else if (mode == 2 || mode == 4 || mode == 6) {
+            const uint32_t kk = mode == 4 ? 0u : (uint32_t)k;
             const uint32_t col = hash32(seed ^ (uint32_t)(blockIdx.x * 64 + wave * 4 + (lane >> 4)) * 8u ^
                                         kk * 0x9E3779B9u) % 2048u;
             w = col * 16u + (uint32_t)(lane & 15);
@@ -73,12 +76,15 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
         }
         a[k] = w & (kWords - 1);
     }
+    const bool on = mode != 6 || (lane & 15) < 3;
     __syncthreads();
     const unsigned long long w0 = wall_clock64();
     const unsigned long long t0 = clock64();
-    for (int it = 0; it < iters; ++it) {
+    if (on) {
+        for (int it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int k = 0; k < kAddr; ++k) atomicAdd(&lds[a[k]], 1u);
+            for (int k = 0; k < kAddr; ++k) atomicAdd(&lds[a[k]], 1u);
+        }
     }
     __syncthreads();
     const unsigned long long t1 = clock64();
@@ -95,15 +101,16 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
 
 extern "C" {
 
-// Run pattern `mode` (0-5) with `blocks` workgroups of 1024 threads, each
-// lane issuing 8 * iters atomics.  Outputs: chip-wide lane-ops per second
-// (HIP events around the launch), mean LDS atomic lanes per shader clock per
-// workgroup (clock64 around the loop), the launch time in ms, and the mean
+// Run pattern `mode` (0-6) with `blocks` workgroups of 1024 threads, each
+// active lane issuing 8 * iters atomics.  Outputs: chip-wide lane-ops per
+// second (HIP events around the launch), mean LDS atomic lanes (active ones)
+// per shader clock per workgroup (clock64 around the loop), the launch time
+// in ms, and the mean
 // shader clock in GHz over the loops (clock64 cycles per wall_clock64 tick
 // times 100 MHz).  Returns 0, or a HIP error code.
 int fhp_lds_atomic(int32_t mode, int32_t iters, int32_t blocks, double *lane_ops_per_s,
                    double *lanes_per_clk, double *ms_out, double *clock_ghz) {
-    if (mode < 0 || mode > 5 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
+    if (mode < 0 || mode > 6 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
     unsigned long long *cyc = nullptr, *tck = nullptr;
     uint32_t *sink = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -135,7 +142,7 @@ int fhp_lds_atomic(int32_t mode, int32_t iters, int32_t blocks, double *lane_ops
         if (e == hipSuccess)
             e = hipMemcpy(w, tck, sizeof(unsigned long long) * (size_t)blocks, hipMemcpyDeviceToHost);
         if (e == hipSuccess) {
-            const double lanes = (double)kThreads * kAddr * (double)iters;
+            const double lanes = (double)kThreads * kAddr * (double)iters * (mode == 6 ? 3.0 / 16.0 : 1.0);
             double sum = 0.0, cyc_sum = 0.0, tick_sum = 0.0;
             for (int b = 0; b < blocks; ++b) {
                 sum += lanes / (double)(h[b] ? h[b] : 1);
