@@ -183,8 +183,8 @@ def cpu_baseline(w, rows_arg, target_s=20.0):
 def lds_probe():
     """Live LDS-atomic microbenchmark: lanes per shader clock per CU, shader
     clocks per wave-wide atomic and the chip-wide rate for three address
-    patterns, and for the tile pattern with 3 of each 16-lane group's lanes
-    active (libfh_probe.so)."""
+    patterns, for the tile pattern with 3 of each 16-lane group's lanes
+    active, and for the tile pattern with ds_add_f32 (libfh_probe.so)."""
     import ctypes
     lib = ctypes.CDLL(PROBE_LIB)
     f = lib.fhp_lds_atomic
@@ -193,9 +193,10 @@ def lds_probe():
     f.restype = ctypes.c_int
     out = {}
     for mode, name, active in [(0, "conflict_free", 64), (1, "random", 64), (2, "tile_pattern", 64),
-                               (6, "tile_pattern_3_of_16_rows", 12)]:
+                               (6, "tile_pattern_3_of_16_rows", 12), (7, "tile_pattern_f32", 64)]:
+        iters = 200 if mode == 7 else 2000  # the float atomics are far slower
         rate, lpc, ms, ghz = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        rc = f(mode, 2000, 1024, ctypes.byref(rate), ctypes.byref(lpc), ctypes.byref(ms), ctypes.byref(ghz))
+        rc = f(mode, iters, 1024, ctypes.byref(rate), ctypes.byref(lpc), ctypes.byref(ms), ctypes.byref(ghz))
         if rc != 0:
             raise RuntimeError("LDS probe failed with HIP error %d" % rc)
         out[name] = {"lanes_per_clk_per_cu": lpc.value, "tops": rate.value / 1e12, "clock_ghz": ghz.value,

@@ -22,6 +22,7 @@
 //   6  the tile pattern with only lanes 0-2 of each group active (a row
 //      block with 3 rows on the grid): 12 of 64 lanes per atomic, to show
 //      whether the pipe's cost follows the active lanes or the instructions
+//   7  the tile pattern with ds_add_f32 (floating-point accumulation)
 // Cycles come from the shader clock (clock64) around the loop, between two
 // workgroup barriers, and the same interval on the constant 100 MHz clock
 // (wall_clock64) gives the shader clock's frequency under this load; the
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
             const int slope8 = (int)(hh >> 16) % 81 - 40;
             const int col = (int)(hh % 1024u) + 512 + ((lane & 15) * slope8 >> 3);
             w = (uint32_t)col * 16u + (uint32_t)(lane & 15);
-        } else if (mode == 2 || mode == 4 || mode == 6) {
+        } else if (mode == 2 || mode == 4 || mode == 6 || mode == 7) {
             const uint32_t kk = mode == 4 ? 0u : (uint32_t)k;
             const uint32_t col = hash32(seed ^ (uint32_t)(blockIdx.x * 64 + wave * 4 + (lane >> 4)) * 8u ^
                                         kk * 0x9E3779B9u) % 2048u;
@@ -80,7 +81,13 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
     __syncthreads();
     const unsigned long long w0 = wall_clock64();
     const unsigned long long t0 = clock64();
-    if (on) {
+    if (mode == 7) {
+        float *fl = reinterpret_cast<float *>(lds);
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < kAddr; ++k) atomicAdd(&fl[a[k]], 1.0f);
+        }
+    } else if (on) {
         for (int it = 0; it < iters; ++it) {
 #pragma unroll
             for (int k = 0; k < kAddr; ++k) atomicAdd(&lds[a[k]], 1u);
@@ -101,7 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_lds_atomic(int32_t mode, int32_t i
 
 extern "C" {
 
-// Run pattern `mode` (0-6) with `blocks` workgroups of 1024 threads, each
+// Run pattern `mode` (0-7) with `blocks` workgroups of 1024 threads, each
 // active lane issuing 8 * iters atomics.  Outputs: chip-wide lane-ops per
 // second (HIP events around the launch), mean LDS atomic lanes (active ones)
 // per shader clock per workgroup (clock64 around the loop), the launch time
@@ -110,7 +117,7 @@ extern "C" {
 // times 100 MHz).  Returns 0, or a HIP error code.
 int fhp_lds_atomic(int32_t mode, int32_t iters, int32_t blocks, double *lane_ops_per_s,
                    double *lanes_per_clk, double *ms_out, double *clock_ghz) {
-    if (mode < 0 || mode > 6 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
+    if (mode < 0 || mode > 7 || iters < 1 || blocks < 1) return (int)hipErrorInvalidValue;
     unsigned long long *cyc = nullptr, *tck = nullptr;
     uint32_t *sink = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
